@@ -1,0 +1,223 @@
+"""Throughput of the linked-cell rigid-molecule force path on one MI355X.
+
+One "step" is one md_step: leapfrog kick/drift (+ rotation), linked-cell rebuild (wrap, bin,
+stable counting sort, sorted gather) and the full force/torque/energy/virial evaluation with its
+deterministic reductions -- every stage of the hot path, on one batch of synthetic input already
+resident in HBM.
+
+Default workload: homogeneous LJ liquid, N = 1,048,576 (FCC 64^3 start with 0.05 sigma jitter),
+rho = 0.75, T = 0.9, r_c = 2.5 (truncated-shifted), cubic periodic box; FP32 pair arithmetic
+(FP64 COM test, accumulation and reductions) timed, FP64 path timed beside it.
+
+Prints ONE JSON line.  Extra fields: steps/s, forces-only interactions/s, FP64-path numbers,
+FP32 errors against the FP64 path (full system) and against the CPU oracle (sampled rows),
+roofline of the pair kernel (timed with HIP events on its launch stream), and the CPU oracle's
+rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12  # MI355X FP32 vector, published (packed-FP32 figure)
+PEAK_FP64 = 78.6e12   # MI355X FP64 vector, published
+PEAK_HBM = 8.0e12
+METRIC = "molecule-pair interactions/s + steps/s, FP32 vs FP64 path at stated force error"
+
+
+def distance_tests(counts3d):
+    """Half-stencil distance-test count D = sum_i n_d(i) - N/2 with
+    n_d(i) = N_i/2 (N_i + sum over the 26 neighbour cells N_j) (load-cost equation, Sec. 4.2)."""
+    c = counts3d.astype(np.float64)
+    nb = np.zeros_like(c)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx or dy or dz:
+                    nb += np.roll(c, (dz, dy, dx), axis=(0, 1, 2))
+    nd = 0.5 * c * (c + nb)
+    return float(nd.sum() - 0.5 * c.sum())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--force-evals", type=int, default=100)
+    ap.add_argument("--workload", default="c2_lj_1m")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle rows timed (0: auto)")
+    ap.add_argument("--quick", action="store_true", help="short run for profilers: few steps, no extras")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.quick:
+        args.steps, args.warmup, args.force_evals = min(args.steps, 5), min(args.warmup, 2), 5
+        args.no_fp64 = args.no_cpu_baseline = True
+
+    import torch
+    from paper_1408_4599_amd import md, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    cfg = W.make(args.workload)
+    gen_s = time.time() - t0
+    N = cfg["pos"].shape[0]
+    dev = lambda a, dt=torch.float64: None if a is None else torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    multi = cfg["quat"] is not None
+    ncomp = len(cfg["model"]["components"])
+    comp_t = dev(cfg["comp"], torch.int32) if ncomp > 1 else None
+    model = md.Model(cfg["model"])
+    cells = md.Cells()
+    print(f"[bench] workload {args.workload}: N={N}, box={cfg['box'].tolist()}, generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    # ---- one reference evaluation of the start configuration (both precisions) ----
+    pos0 = dev(cfg["pos"])
+    quat0 = dev(cfg["quat"])
+    md.build_cells(model, cells, pos0, quat0, comp_t, cfg["box"])
+    r64 = md.forces(model, cells, "fp64", torque=multi, per_molecule=False)
+    r32 = md.forces(model, cells, "fp32", torque=multi, per_molecule=False)
+    torch.cuda.synchronize()
+    P = int(r64["npairs"].item())
+    assert P == int(r32["npairs"].item())
+    v = cells.view()
+    counts = np.diff(v["cell_start"].cpu().numpy()).reshape(v["nc"][2], v["nc"][1], v["nc"][0])
+    D = distance_tests(counts)
+    F64, F32 = r64["force"].double(), r32["force"].double()
+    eF = float(torch.linalg.norm(F32 - F64) / torch.linalg.norm(F64))
+    U64, U32 = float(r64["uw"][0]), float(r32["uw"][0])
+    eU = abs(U32 - U64) / abs(U64)
+    errors = {"fp32_vs_fp64_gpu": {"force_rel_rms": eF, "energy_rel": eU,
+                                   "virial_rel": abs(float(r32["uw"][1]) - float(r64["uw"][1])) / abs(float(r64["uw"][1]))}}
+    if multi:
+        T64, T32 = r64["torque"], r32["torque"]
+        errors["fp32_vs_fp64_gpu"]["torque_rel_rms"] = float(torch.linalg.norm(T32 - T64) / torch.linalg.norm(T64))
+    print(f"[bench] P={P} D={D:.4g} eps_F={eF:.2e} eps_U={eU:.2e}", file=sys.stderr, flush=True)
+
+    # ---- forces-only timing: pair kernel with HIP events on its stream ----
+    def time_forces(prec, n):
+        out = {"force": torch.empty((N, 3), dtype=torch.float64, device="cuda"),
+               "uw": torch.empty(5, dtype=torch.float64, device="cuda"),
+               "npairs": torch.empty(1, dtype=torch.int64, device="cuda")}
+        if multi:
+            out["torque"] = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            md.forces_into(model, cells, prec, out)
+        torch.cuda.synchronize()
+        model.profile(True)
+        t = time.perf_counter()
+        for _ in range(n):
+            md.forces_into(model, cells, prec, out)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / n
+        ms, k = model.profile_read("pair")
+        model.profile(False)
+        return wall, ms / k / 1e3
+
+    f32_wall, f32_pair = time_forces("fp32", args.force_evals)
+    f64_wall, f64_pair = (None, None) if args.no_fp64 else time_forces("fp64", args.force_evals)
+
+    # ---- full steps ----
+    def run_steps(prec):
+        pos = dev(cfg["pos"])
+        vel = dev(cfg["vel"])
+        quat = dev(cfg["quat"])
+        ang = dev(cfg["angmom"])
+        en = torch.empty((max(args.steps, args.warmup, 1), 4), dtype=torch.float64, device="cuda")
+        if args.warmup:
+            md.step(model, cells, pos, vel, quat, ang, comp_t, cfg["box"], cfg["dt"], args.warmup, prec, en)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        md.step(model, cells, pos, vel, quat, ang, comp_t, cfg["box"], cfg["dt"], args.steps, prec, en)
+        torch.cuda.synchronize()
+        dt_ = time.perf_counter() - t
+        e = en[:args.steps].cpu().numpy()
+        return dt_, e
+
+    t32, e32 = run_steps("fp32")
+    print(f"[bench] fp32 steps: {args.steps} in {t32:.3f}s", file=sys.stderr, flush=True)
+    t64 = e64 = None
+    if not args.no_fp64:
+        t64, e64 = run_steps("fp64")
+        print(f"[bench] fp64 steps: {args.steps} in {t64:.3f}s", file=sys.stderr, flush=True)
+
+    ms_per_step = 1e3 * t32 / args.steps
+    value = P * args.steps / t32
+    E = e32[:, 0] + e32[:, 1] + e32[:, 2]
+    W_alg = 8.0 * D + 24.0 * P
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "N": N, "box": cfg["box"].tolist(), "rc": cfg["model"]["rc"],
+                   "lj_shift": cfg["model"]["lj_shift"], "dt": cfg["dt"], "T": cfg["T"],
+                   "cells": list(v["nc"]), "interacting_pairs": P, "distance_tests_half_shell": D,
+                   "note": "interactions/s = unique COM-cutoff pairs x steps / wall time of md_step (cell rebuild, "
+                           "forces and leapfrog every step); f32 site-site arithmetic, f64 COM test and sums"},
+        "steps_per_s": args.steps / t32,
+        "forces_only": {"fp32_interactions_per_s": P / f32_wall, "fp32_ms": 1e3 * f32_wall,
+                        "fp32_pair_kernel_ms": 1e3 * f32_pair},
+        "errors": errors,
+        "nve_rel_energy_spread_fp32": float(np.abs(E - E[0]).max() / abs(E[0])),
+        "roofline": {"bound": "alu", "achieved": W_alg / f32_pair / 1e12, "peak": PEAK_FP32 / 1e12,
+                     "unit": "TFLOP/s", "frac": W_alg / f32_pair / PEAK_FP32, "traffic": None,
+                     "kernel": "k_pair_lj1<float>" if model.single_site else "k_pair_ms<float>",
+                     "algorithmic_flop_per_launch": W_alg,
+                     "accounting": "8 FLOP per half-shell distance test (D) + 24 FLOP per unique interacting pair (P)",
+                     "frac_of_nonpacked_fp32_issue": W_alg / f32_pair / (PEAK_FP32 / 2)},
+    }
+    if not args.no_fp64:
+        out["fp64"] = {"interactions_per_s": P * args.steps / t64, "ms_per_step": 1e3 * t64 / args.steps,
+                       "steps_per_s": args.steps / t64, "forces_only_interactions_per_s": P / f64_wall,
+                       "pair_kernel_ms": 1e3 * f64_pair,
+                       "roofline_frac_fp64_peak": W_alg / f64_pair / PEAK_FP64}
+        out["fp32_speedup_over_fp64"] = {"step": t64 / t32, "pair_kernel": f64_pair / f32_pair}
+
+    # ---- oracle rows: FP32 errors on a sample and the CPU baseline ----
+    if not args.no_cpu_baseline:
+        from oracle import oracle as O
+        rng = np.random.default_rng(7)
+        ns = args.cpu_sample or max(64, int(2.0e9 / N))
+        idx = np.sort(rng.choice(N, size=min(ns, N), replace=False))
+        t = time.perf_counter()
+        ref = O.rows(cfg["model"], cfg["pos"], cfg["quat"], cfg["comp"], cfg["box"], idx)
+        tcpu = time.perf_counter() - t
+        F32s = F32.cpu().numpy()[idx]
+        errors["fp32_vs_oracle_rows"] = {
+            "rows": int(len(idx)),
+            "force_rel_rms": float(np.linalg.norm(F32s - ref["F"]) / np.linalg.norm(ref["F"])),
+            "fp64_force_rel_rms": float(np.linalg.norm(F64.cpu().numpy()[idx] - ref["F"]) / np.linalg.norm(ref["F"]))}
+        t_full = tcpu * N / len(idx)
+        out["cpu_baseline"] = {"value": P / t_full, "unit": "interactions/s", "cores": O.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"{len(idx)} of {N} molecules: full O(N) rows of the FP64 brute-force "
+                                         f"oracle in {tcpu:.1f}s; rate scaled to all N rows (each pair visited "
+                                         f"from both ends)"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

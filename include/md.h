@@ -1,0 +1,206 @@
+/*
+ * md.h -- C ABI of libmdcell: linked-cell short-range forces for rigid multi-centre molecules
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (ls1 mardyn, Niethammer et al., JCTC 2014):
+ *   - molecules are rigid rotators: a centre of mass (COM) and an orientation quaternion, no
+ *     internal degrees of freedom (Sec. 2, first paragraph; quaternions in Sec. 3, Eqs. 4-5);
+ *   - interaction sites per molecule type: Lennard-Jones 12-6 sites (Sec. 2, LJ equation),
+ *     optionally truncated and shifted (LJTS), Lorentz-Berthelot mixing with binary interaction
+ *     parameters; point charges, point dipoles and linear point quadrupoles (Sec. 2, multipole
+ *     paragraph), units with k_B = k_C = 1 (Sec. 2, Table 1);
+ *   - reaction field for dipoles (Sec. 3, second paragraph);
+ *   - neighbour search with linked cells of edge >= r_c and periodic boundaries (Sec. 3,
+ *     linked-cell paragraphs); the cutoff acts on the COM distance;
+ *   - per-molecule forces and torques by summation over pairs (Sec. 3, after Fig. 1);
+ *   - leapfrog integration of translation and quaternion rotation (Sec. 3, Eqs. 2-5).
+ *
+ * Conventions for every entry point:
+ *   - Arrays are DEVICE pointers (hipMalloc'd or a torch CUDA tensor's data_ptr()) unless the
+ *     comment says "host".  All device arrays are dense, row-major, FP64 unless typed otherwise.
+ *   - Calls that take `stream` (a hipStream_t, NULL = the legacy default stream) enqueue work on
+ *     it and return without synchronising, except where a comment says "syncs".
+ *   - Every call returns MD_OK (0) or a negative MD_E* code; the thread-local text of the last
+ *     failure is returned by md_last_error().  No exception or abort crosses the ABI.
+ *   - Host-checkable errors (NULL pointers, sizes, box too small) are reported synchronously
+ *     before anything is enqueued.  Errors only the device can see (non-finite coordinates,
+ *     component ids out of range, non-unit quaternions) raise bits of a device status word that
+ *     md_status() reads (syncs); with MD_CHECK in the model flags every call syncs and checks it.
+ *   - Quaternions are scalar-first (w, x, y, z) and rotate body-frame vectors into the space
+ *     frame with the polynomial matrix A(q) (no normalisation inside); gradients with respect
+ *     to quaternions are taken with respect to the four raw components.
+ *   - Output arrays indexed by molecule are written in the caller's ORIGINAL molecule order.
+ *   - One md_model (and the md_cells used with it) per stream at a time; calls on one model from
+ *     several host threads must be serialised by the caller.
+ */
+#ifndef MDCELL_MD_H
+#define MDCELL_MD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MD_OK = 0,
+  MD_EINVAL = -1,      /* NULL required pointer, N <= 0, r_c <= 0, bad precision, bad table */
+  MD_EBOX = -2,        /* a box side holds fewer than three cells of edge > r_c */
+  MD_ECOMP = -3,       /* component table exceeds the compiled limits below */
+  MD_ENONFINITE = -4,  /* non-finite host argument (box, r_c, dt, table entry) */
+  MD_EHIP = -5,        /* HIP runtime error; text in md_last_error() */
+  MD_ENOMEM = -6,      /* device allocation failed */
+  MD_EDEVICE = -7      /* device status word non-zero (only with MD_CHECK or md_status) */
+};
+
+/* md_model_create flags */
+#define MD_LJ_SHIFT 0x1u /* LJTS: subtract u_ab(r_c) from every LJ site pair inside the cutoff */
+#define MD_CHECK 0x2u    /* validate inputs on the device and sync after every call */
+
+/* precision argument */
+#define MD_FP64 0 /* all pair arithmetic and accumulation in FP64 */
+#define MD_FP32 1 /* site-site arithmetic in FP32; COM test, accumulation and reductions in FP64 */
+
+/* device status word bits (md_status) */
+#define MD_DEV_NONFINITE 0x1 /* a position was NaN/Inf */
+#define MD_DEV_COMP 0x2      /* a component id was outside [0, ncomp) */
+#define MD_DEV_QUAT 0x4      /* | |q|^2 - 1 | > 1e-6 for some molecule */
+#define MD_DEV_CAPACITY 0x8  /* internal capacity exceeded (should not happen) */
+
+/* compiled limits of the component table */
+#define MD_MAX_COMP 4
+#define MD_MAX_LJ 4
+#define MD_MAX_CHG 4
+#define MD_MAX_DIP 2
+#define MD_MAX_QUAD 2
+
+/* One rigid molecule type (host memory, body frame: COM at the origin, principal axes = body
+ * axes).  LJ sites meet LJ sites only; charges, dipoles and quadrupoles meet each other. */
+typedef struct {
+  int32_t n_lj, n_chg, n_dip, n_quad;
+  const double *lj_pos;   /* [n_lj][3] site offsets from the COM */
+  const double *lj_eps;   /* [n_lj] epsilon_a > 0 */
+  const double *lj_sigma; /* [n_lj] sigma_a > 0 */
+  const double *chg_pos;  /* [n_chg][3] */
+  const double *chg_q;    /* [n_chg] charge */
+  const double *dip_pos;  /* [n_dip][3] */
+  const double *dip_dir;  /* [n_dip][3] unit axis */
+  const double *dip_mu;   /* [n_dip] dipole moment */
+  const double *quad_pos; /* [n_quad][3] */
+  const double *quad_dir; /* [n_quad][3] unit axis */
+  const double *quad_Q;   /* [n_quad] linear quadrupole moment (phi = Q P2(cos theta) / r^3) */
+  double mass;            /* > 0 */
+  double inertia[3];      /* principal moments; 0 allowed (axis of a linear molecule) */
+} md_component_desc;
+
+typedef struct md_model md_model; /* opaque: device copy of the model tables + scratch */
+typedef struct md_cells md_cells; /* opaque: cell grid + molecules sorted into cells */
+
+/* Read-only view of a built cell grid (device pointers owned by the md_cells object, valid until
+ * the next md_build_cells / md_cells_destroy on it).  Cells have edge h_k = L_k / n_k > r_c,
+ * n_k = floor(L_k / r_c) reduced until h_k >= r_c (1 + 2^-30); linear cell id
+ * (c_z n_y + c_y) n_x + c_x.  Molecules are sorted stably by cell: within a cell by original
+ * index. */
+typedef struct {
+  int64_t N;
+  int64_t ncell;
+  int32_t nc[3];
+  double box[3];
+  const int32_t *cell_of;    /* [N] cell of each molecule, original order */
+  const int32_t *cell_start; /* [ncell + 1] first sorted slot of each cell */
+  const int32_t *perm;       /* [N] original index of the molecule in each sorted slot */
+} md_cells_info;
+
+/* Create a model from ncomp host component descriptions (Sec. 2).  xi, eta: host
+ * [ncomp][ncomp] Berthelot / Lorentz binary factors (symmetric), NULL for all ones: pair
+ * epsilon_ab = xi_AB sqrt(eps_a eps_b), sigma_ab = eta_AB (sigma_a + sigma_b) / 2.  rc: COM
+ * cutoff.  eps_rf: reaction-field permittivity, INFINITY allowed, applied to dipole-dipole site
+ * pairs of molecule pairs inside the cutoff as -kappa mu_a.mu_b / r_c^3 with
+ * kappa = 2 (eps_rf - 1) / (2 eps_rf + 1) (kappa = 1 at infinity).  flags: MD_LJ_SHIFT,
+ * MD_CHECK.  *out receives the model (owned by the caller, free with md_model_destroy).
+ * Allocates device memory on the current device.  Errors: MD_EINVAL, MD_ECOMP, MD_ENONFINITE,
+ * MD_ENOMEM, MD_EHIP. */
+int md_model_create(const md_component_desc *comps, int32_t ncomp, const double *xi, const double *eta, double rc,
+                    double eps_rf, uint32_t flags, md_model **out);
+int md_model_destroy(md_model *m);
+
+/* Number of doubles md_forces_adjoint writes to dparams, and the offset of each block:
+ * for component c in order, for each LJ site [deps, dsigma, dx, dy, dz], then each charge
+ * [dq, dx, dy, dz], each dipole [dmu, dx, dy, dz], each quadrupole [dQ, dx, dy, dz]
+ * (dx, dy, dz: derivative w.r.t. the body-frame site offset). */
+int64_t md_param_count(const md_model *m);
+
+int md_cells_create(md_cells **out);
+int md_cells_destroy(md_cells *c);
+int md_cells_view(const md_cells *c, md_cells_info *out);
+
+/* Linked-cell build (Sec. 3, linked-cell paragraph; periodic boundaries): wrap every COM into
+ * [0, L_k) as x - L floor(x / L) (minus L once more if rounding left it at L), assign cell
+ * c_k = min(n_k - 1, floor(x_w * (n_k / L_k))), counting-sort the molecules stably into cells
+ * and gather sorted structure-of-arrays copies: wrapped COMs, component ids and, for multi-site
+ * models, world-frame site offsets A(q) d_a and axes A(q) e_a.
+ *   pos  [N][3] COM positions (any real values; wrapped copies are taken)
+ *   quat [N][4] orientations, or NULL if every component is a single site at its COM
+ *   comp [N] component ids (int32), or NULL if ncomp == 1
+ *   box  host [3] periodic box lengths
+ * Grows the cells' buffers on demand (hipMalloc), otherwise allocation-free.  Errors: MD_EINVAL,
+ * MD_EBOX, MD_ENONFINITE, MD_ENOMEM, MD_EHIP. */
+int md_build_cells(md_model *m, md_cells *cells, const double *pos, const double *quat, const int32_t *comp,
+                   int64_t N, const double box[3], void *stream);
+
+/* Forces, torques, energy and virial of the built configuration (Sec. 3): every molecule pair
+ * whose minimum-image COM distance r satisfies fma(dz,dz,fma(dy,dy,dx*dx)) < r_c*r_c
+ * interacts through all its site pairs.
+ *   precision MD_FP64 or MD_FP32
+ *   force   [N][3]  sum of site forces on each molecule (required)
+ *   torque  [N][3]  torque about the COM (NULL allowed; required content only for multi-site)
+ *   u_mol   [N]     half of the pair energies of each molecule (NULL allowed)
+ *   w_mol   [N]     half of the molecular virials r_ij . F_ij of each molecule (NULL allowed)
+ *   nnb_mol [N]     int32 number of partners inside the cutoff (NULL allowed)
+ *   uw      [5]     U, W, W_xx, W_yy, W_zz (required; FP64, deterministic fixed-order sums)
+ *   npairs  [1]     int64 number of unordered interacting pairs (NULL allowed)
+ * Results are bitwise reproducible run to run.  Errors: MD_EINVAL, MD_EHIP, MD_EDEVICE. */
+int md_forces(md_model *m, const md_cells *cells, int precision, double *force, double *torque, double *u_mol,
+              double *w_mol, int32_t *nnb_mol, double *uw, int64_t *npairs, void *stream);
+
+/* nsteps leapfrog steps (Sec. 3, Eqs. 2-5), each: build cells, forces/torques at t,
+ *   v(t + dt/2) = v(t - dt/2) + dt F / m,  r(t + dt) = r(t) + dt v(t + dt/2)  (wrapped),
+ * and for molecules with inertia, Fincham's rotational leapfrog with the space-frame angular
+ * momentum j: j(t) = j(t - dt/2) + dt/2 tau;  q(t + dt/2) = normalise(q + dt/2 qdot(q, w(t)));
+ * j(t + dt/2) = j(t - dt/2) + dt tau;  q(t + dt) = normalise(q + dt qdot(q(t + dt/2),
+ * w(t + dt/2))), qdot(q, w) = q (x) (0, w_body) / 2, w_body = I^-1 A(q)^T j (I_k^-1 := 0 where
+ * I_k = 0).  pos, vel [N][3], quat [N][4] (NULL for single-site models), angmom [N][3] (NULL
+ * likewise) are updated in place.  energies [nsteps][4] (NULL allowed) receives per step
+ * U(t), K_trans(t) (v(t) = mean of the half-step velocities), K_rot(t), W(t).  Errors as
+ * md_build_cells and md_forces. */
+int md_step(md_model *m, md_cells *cells, double *pos, double *vel, double *quat, double *angmom,
+            const int32_t *comp, int64_t N, const double box[3], double dt, int64_t nsteps, int precision,
+            double *energies, void *stream);
+
+/* Gradient of gU * U for the built configuration, recomputing every pair (no stored pair list):
+ *   dpos    [N][3]  gU dU/dr_i (= -gU F_i)
+ *   dquat   [N][4]  gU dU/dq_i with respect to the raw quaternion components (NULL allowed)
+ *   dparams [md_param_count(m)] gU dU/d(parameters), layout as md_param_count (NULL allowed)
+ * The molecule-pair set is the one fixed by the cutoff (U is differentiated piecewise).
+ * Errors: MD_EINVAL, MD_EHIP. */
+int md_forces_adjoint(md_model *m, const md_cells *cells, int precision, double gU, double *dpos, double *dquat,
+                      double *dparams, void *stream);
+
+/* Synchronises the model's last stream, returns the device status word in *flags (host) and
+ * clears it.  Returns MD_OK, or MD_EHIP. */
+int md_status(md_model *m, int32_t *flags);
+
+/* Kernel timing with HIP events recorded on the launch stream around the pair kernel and around
+ * the cell build.  md_profile(m, 1) starts (and clears) recording; md_profile_read syncs and
+ * returns the total milliseconds and launch counts of the pair kernels ("pair"), the cell
+ * build ("build"), the leapfrog kernels ("step") and the adjoint kernels ("adjoint"). */
+int md_profile(md_model *m, int enable);
+int md_profile_read(md_model *m, const char *group, double *total_ms, int64_t *launches);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *md_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

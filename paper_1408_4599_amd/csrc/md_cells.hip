@@ -1,0 +1,275 @@
+// Linked-cell build: periodic wrap, cell assignment, stable counting sort into cells, and the
+// sorted structure-of-arrays gather with the world-frame site transform (Sec. 3, linked-cell
+// paragraphs; periodic boundaries; rigid molecules oriented by quaternions, Sec. 3 Eqs. 4-5).
+//
+// HBM-bound: per molecule the build reads the COM (24 B), id/slot words and, for multi-site
+// models, the quaternion (32 B) and component id, and writes cell id, slot, permutation and the
+// sorted COM copy (24 B) plus site vectors.  Launch shapes are 256-thread blocks over molecules.
+
+#include "md_internal.h"
+
+namespace mdcell {
+namespace {
+
+__device__ __forceinline__ int bin1(double xw, double inv_h, int n) {
+  int c = (int)floor(xw * inv_h);
+  return c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
+}
+
+struct BinArgs {
+  const double *pos, *quat;
+  const int32_t *comp;
+  int64_t N;
+  double Lx, Ly, Lz, ihx, ihy, ihz;
+  int32_t nx, ny, nz, ncomp, check_quat;
+  int32_t *cell_of, *slot, *count, *status;
+};
+
+// Wrap + bin + per-cell histogram.  The returned atomic slot is only a provisional position;
+// the final order inside a cell is fixed by k_rank_gather.
+__global__ __launch_bounds__(256) void k_bin(BinArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.N) return;
+  double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
+  int flags = 0;
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+    flags |= MD_DEV_NONFINITE;
+    x = y = z = 0.0;
+  }
+  if (a.comp) {
+    const int32_t c = a.comp[i];
+    if (c < 0 || c >= a.ncomp) flags |= MD_DEV_COMP;
+  }
+  if (a.check_quat && a.quat) {
+    const double *q = a.quat + 4 * i;
+    const double n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    if (!(fabs(n2 - 1.0) <= 1e-6)) flags |= MD_DEV_QUAT;
+  }
+  if (flags) atomicOr(a.status, flags);
+  const int cx = bin1(wrap1(x, a.Lx), a.ihx, a.nx);
+  const int cy = bin1(wrap1(y, a.Ly), a.ihy, a.ny);
+  const int cz = bin1(wrap1(z, a.Lz), a.ihz, a.nz);
+  const int cell = (cz * a.ny + cy) * a.nx + cx;
+  a.cell_of[i] = cell;
+  a.slot[i] = atomicAdd(a.count + cell, 1);
+}
+
+// ---------------------------------------------------------------- exclusive scan of counts
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_TILE = SCAN_ITEMS * SCAN_THREADS;
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Block-local exclusive scan of a tile of SCAN_TILE counts; the tile total goes to bsum[b].
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_local(const int32_t *in, int64_t n, int32_t *out,
+                                                             int32_t *bsum) {
+  __shared__ int wsum[SCAN_THREADS / 64];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  int v[SCAN_ITEMS];
+  int tsum = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    tsum += v[k];
+  }
+  const int incl = wave_incl_scan(tsum);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int woff = 0;
+  for (int k = 0; k < w; ++k) woff += wsum[k];
+  int run = woff + incl - tsum;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == SCAN_THREADS - 1) bsum[blockIdx.x] = woff + incl;
+}
+
+// Exclusive scan of the nb tile totals in place (one block, sequential over chunks), total to
+// out[n].
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(int32_t *bsum, int64_t nb, int32_t *out, int64_t n) {
+  __shared__ int wsum[SCAN_THREADS / 64];
+  __shared__ int carry_s;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < nb; c0 += SCAN_THREADS) {
+    const int64_t i = c0 + threadIdx.x;
+    const int v = i < nb ? bsum[i] : 0;
+    const int incl = wave_incl_scan(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    int woff = 0;
+    for (int k = 0; k < w; ++k) woff += wsum[k];
+    const int carry = carry_s;
+    if (i < nb) bsum[i] = carry + woff + incl - v;
+    __syncthreads();
+    if (threadIdx.x == SCAN_THREADS - 1) carry_s = carry + woff + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = carry_s;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_add(int32_t *out, int64_t n, const int32_t *bsum) {
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
+  const int add = bsum[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k)
+    if (base + k < n) out[base + k] += add;
+}
+
+// ---------------------------------------------------------------- stable placement + gather
+__global__ __launch_bounds__(256) void k_scatter(const int32_t *cell_of, const int32_t *slot, const int32_t *start,
+                                                 int64_t N, int32_t *tmp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  tmp[start[cell_of[i]] + slot[i]] = (int32_t)i;
+}
+
+struct GatherArgs {
+  const double *pos, *quat;
+  const int32_t *comp, *cell_of, *start, *tmp;
+  int64_t N;
+  double Lx, Ly, Lz;
+  const ModelDev *md;
+  int32_t sl, sc, sd, sq, nvec;
+  int32_t *perm, *scomp;
+  double *sx, *sy, *sz, *svec;
+};
+
+__device__ __forceinline__ void rotate(const double q[4], const double v[3], double o[3]) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  o[0] = (w * w + x * x - y * y - z * z) * v[0] + 2.0 * (x * y - w * z) * v[1] + 2.0 * (x * z + w * y) * v[2];
+  o[1] = 2.0 * (x * y + w * z) * v[0] + (w * w - x * x + y * y - z * z) * v[1] + 2.0 * (y * z - w * x) * v[2];
+  o[2] = 2.0 * (x * z - w * y) * v[0] + 2.0 * (y * z + w * x) * v[1] + (w * w - x * x - y * y + z * z) * v[2];
+}
+
+// Final position of molecule i inside its cell = number of molecules of the same cell with a
+// smaller original index (a stable counting sort); then gather the sorted copies.
+__global__ __launch_bounds__(256) void k_rank_gather(GatherArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.N) return;
+  const int c = a.cell_of[i];
+  const int s = a.start[c], n = a.start[c + 1] - s;
+  int rank = 0;
+  for (int k = 0; k < n; ++k) rank += (a.tmp[s + k] < (int32_t)i) ? 1 : 0;
+  const int d = s + rank;
+  a.perm[d] = (int32_t)i;
+  double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) x = y = z = 0.0;
+  a.sx[d] = wrap1(x, a.Lx);
+  a.sy[d] = wrap1(y, a.Ly);
+  a.sz[d] = wrap1(z, a.Lz);
+  int ci = 0;
+  if (a.comp) {
+    ci = a.comp[i];
+    if (ci < 0 || ci >= a.md->ncomp) ci = 0;
+  }
+  if (a.scomp) a.scomp[d] = ci;
+  if (a.svec) {
+    const CompDev &cd = a.md->comp[ci];
+    double q[4] = {1.0, 0.0, 0.0, 0.0};
+    if (a.quat)
+      for (int k = 0; k < 4; ++k) q[k] = a.quat[4 * i + k];
+    double *out = a.svec + (int64_t)d * a.nvec * 3;
+    double o[3];
+    const double zero[3] = {0.0, 0.0, 0.0};
+    int v = 0;
+    for (int k = 0; k < a.sl; ++k, ++v) {
+      rotate(q, k < cd.n_lj ? cd.lj_pos[k] : zero, o);
+      out[3 * v] = o[0], out[3 * v + 1] = o[1], out[3 * v + 2] = o[2];
+    }
+    for (int k = 0; k < a.sc; ++k, ++v) {
+      rotate(q, k < cd.n_chg ? cd.chg_pos[k] : zero, o);
+      out[3 * v] = o[0], out[3 * v + 1] = o[1], out[3 * v + 2] = o[2];
+    }
+    for (int k = 0; k < a.sd; ++k, ++v) {
+      rotate(q, k < cd.n_dip ? cd.dip_pos[k] : zero, o);
+      out[3 * v] = o[0], out[3 * v + 1] = o[1], out[3 * v + 2] = o[2];
+    }
+    for (int k = 0; k < a.sd; ++k, ++v) {
+      rotate(q, k < cd.n_dip ? cd.dip_dir[k] : zero, o);
+      out[3 * v] = o[0], out[3 * v + 1] = o[1], out[3 * v + 2] = o[2];
+    }
+    for (int k = 0; k < a.sq; ++k, ++v) {
+      rotate(q, k < cd.n_quad ? cd.quad_pos[k] : zero, o);
+      out[3 * v] = o[0], out[3 * v + 1] = o[1], out[3 * v + 2] = o[2];
+    }
+    for (int k = 0; k < a.sq; ++k, ++v) {
+      rotate(q, k < cd.n_quad ? cd.quad_dir[k] : zero, o);
+      out[3 * v] = o[0], out[3 * v + 1] = o[1], out[3 * v + 2] = o[2];
+    }
+  }
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f64(double *p, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_scale_copy(const double *src, double *dst, int64_t n, double a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = a * src[i];
+}
+
+inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+int launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return MD_OK;
+  k_fill_i32<<<nblk(n, 256), 256, 0, s>>>(p, n, v);
+  return check_hip(hipGetLastError(), "k_fill_i32");
+}
+
+int launch_fill_f64(double *p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return MD_OK;
+  k_fill_f64<<<nblk(n, 256), 256, 0, s>>>(p, n, v);
+  return check_hip(hipGetLastError(), "k_fill_f64");
+}
+
+int launch_scale_copy(const double *src, double *dst, int64_t n, double a, hipStream_t s) {
+  if (n <= 0) return MD_OK;
+  k_scale_copy<<<nblk(n, 256), 256, 0, s>>>(src, dst, n, a);
+  return check_hip(hipGetLastError(), "k_scale_copy");
+}
+
+int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat, const int32_t *comp, int64_t N,
+                 const double inv_h[3], hipStream_t s) {
+  int rc;
+  if ((rc = launch_fill_i32(c->count, c->ncell, 0, s))) return rc;
+  BinArgs b{pos, quat, comp, N, c->box[0], c->box[1], c->box[2], inv_h[0], inv_h[1], inv_h[2], c->nc[0], c->nc[1],
+            c->nc[2], m->host.ncomp, (int32_t)((m->flags & MD_CHECK) != 0), c->cell_of, c->slot, c->count, m->status};
+  k_bin<<<nblk(N, 256), 256, 0, s>>>(b);
+  if ((rc = check_hip(hipGetLastError(), "k_bin"))) return rc;
+  const int64_t nb = (c->ncell + SCAN_TILE - 1) / SCAN_TILE;
+  k_scan_local<<<(unsigned)nb, SCAN_THREADS, 0, s>>>(c->count, c->ncell, c->start, c->bsum);
+  k_scan_top<<<1, SCAN_THREADS, 0, s>>>(c->bsum, nb, c->start, c->ncell);
+  k_scan_add<<<(unsigned)nb, SCAN_THREADS, 0, s>>>(c->start, c->ncell, c->bsum);
+  if ((rc = check_hip(hipGetLastError(), "k_scan"))) return rc;
+  k_scatter<<<nblk(N, 256), 256, 0, s>>>(c->cell_of, c->slot, c->start, N, c->tmp);
+  if ((rc = check_hip(hipGetLastError(), "k_scatter"))) return rc;
+  GatherArgs g{pos, m->single_site ? nullptr : quat, comp, c->cell_of, c->start, c->tmp, N, c->box[0], c->box[1],
+               c->box[2], m->dev, m->shape.lj, m->shape.chg, m->shape.dip, m->shape.quad, c->nvec, c->perm,
+               m->single_site ? nullptr : c->scomp, c->sx, c->sy, c->sz, m->single_site ? nullptr : c->svec};
+  k_rank_gather<<<nblk(N, 256), 256, 0, s>>>(g);
+  return check_hip(hipGetLastError(), "k_rank_gather");
+}
+
+}  // namespace mdcell

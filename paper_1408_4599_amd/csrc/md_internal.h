@@ -1,0 +1,167 @@
+// Internal declarations shared by the libmdcell translation units (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/md.h"
+
+namespace mdcell {
+
+// Site kinds as compile-time tags.
+enum Kind : int { KIND_CHG = 1, KIND_DIP = 2, KIND_QUAD = 3 };
+
+// Per-molecule vector slots of the sorted site arrays: LJ offsets, charge offsets, dipole
+// offsets, dipole axes, quadrupole offsets, quadrupole axes, each group sized by the model's
+// layout shape (SL, SC, SD, SQ).
+struct Shape {
+  int lj, chg, dip, quad;
+  int nvec() const { return lj + chg + 2 * dip + 2 * quad; }
+};
+
+// One component as the kernels see it (FP64, body frame).
+struct CompDev {
+  int32_t n_lj, n_chg, n_dip, n_quad;
+  int32_t rotates;  // any principal moment > 0
+  int32_t pad_[3];
+  double lj_pos[MD_MAX_LJ][3], lj_eps[MD_MAX_LJ], lj_sig[MD_MAX_LJ];
+  double chg_pos[MD_MAX_CHG][3], chg_q[MD_MAX_CHG];
+  double dip_pos[MD_MAX_DIP][3], dip_dir[MD_MAX_DIP][3], dip_mu[MD_MAX_DIP];
+  double quad_pos[MD_MAX_QUAD][3], quad_dir[MD_MAX_QUAD][3], quad_Q[MD_MAX_QUAD];
+  double mass, inv_mass, inertia[3], inv_inertia[3];
+};
+
+// LJ parameters of one site pair (a of component A, b of component B) after mixing.
+struct LJPair {
+  double eps4, eps24, sig2, shift;
+};
+
+struct ModelDev {
+  int32_t ncomp, lj_shift;
+  int32_t sl, sc, sd, sq;  // layout shape of the sorted site vectors
+  double rc, rc2, kappa, kappa_rc3;  // kappa_rc3 = kappa / rc^3
+  double xi[MD_MAX_COMP][MD_MAX_COMP], eta[MD_MAX_COMP][MD_MAX_COMP];
+  CompDev comp[MD_MAX_COMP];
+  LJPair lj[MD_MAX_COMP][MD_MAX_COMP][MD_MAX_LJ][MD_MAX_LJ];
+  // sum of the LJTS shifts u_ab(r_c) over all LJ site pairs of a component pair: subtracted once
+  // per interacting molecule pair in FP64 (a per-pair rounded constant would bias U)
+  double shift_sum[MD_MAX_COMP][MD_MAX_COMP];
+};
+
+// Everything a pair kernel needs about the sorted configuration.
+struct CellsDev {
+  const int32_t *cell_start, *perm, *scomp;
+  const double *sx, *sy, *sz;  // wrapped COMs in sorted order
+  const double *svec;          // [N][nvec][3] world-frame site offsets / axes, sorted order
+  int32_t nx, ny, nz, ncell, nvec;
+  double Lx, Ly, Lz;
+};
+
+struct PairOut {
+  double *force, *torque, *u_mol, *w_mol;
+  int32_t *nnb_mol;
+  double *partial;  // [gridDim.x][PARTIAL_COLS]
+};
+constexpr int PARTIAL_COLS = 5;  // u, wxx, wyy, wzz, nnb
+
+struct AdjOut {
+  double gU;
+  double *dpos, *dquat;
+  double *pgrad;  // [nblocks][nparam] per-block parameter partials (or nullptr)
+};
+
+}  // namespace mdcell
+
+// Library-owned objects behind the opaque handles.
+struct md_cells {
+  int64_t N = 0, cap_N = 0;
+  int64_t ncell = 0, cap_cell = 0, cap_blocks = 0;
+  int32_t nc[3] = {0, 0, 0};
+  double box[3] = {0, 0, 0};
+  int nvec = 0, cap_nvec = 0;
+  bool built = false;
+  const md_model *model = nullptr;
+  int32_t *cell_of = nullptr, *slot = nullptr, *tmp = nullptr, *perm = nullptr, *scomp = nullptr;
+  int32_t *count = nullptr, *start = nullptr, *bsum = nullptr;
+  double *sx = nullptr, *sy = nullptr, *sz = nullptr, *svec = nullptr;
+};
+
+struct md_model {
+  mdcell::ModelDev host;        // host copy of the device tables
+  mdcell::ModelDev *dev = nullptr;
+  mdcell::Shape shape{1, 0, 0, 0};
+  bool single_site = true;      // one component, one LJ site at the COM
+  bool fixed_shape = false;     // one component whose shape has a compiled kernel
+  int64_t nparam = 0;
+  std::vector<int64_t> param_off;  // per component offset into the parameter vector
+  uint32_t flags = 0;
+  int32_t *status = nullptr;    // device status word
+  double *partial = nullptr;    // pair-kernel block partials
+  int64_t cap_partial = 0;
+  double *red2 = nullptr;       // second-stage reduction buffer
+  double *pgrad = nullptr;      // adjoint parameter partials
+  int64_t cap_pgrad = 0;
+  // md_step scratch
+  double *force = nullptr, *torque = nullptr, *uw = nullptr;
+  int64_t cap_step = 0;
+  // profiling
+  bool profiling = false;
+  struct Ev {
+    int group;
+    hipEvent_t a, b;
+  };
+  std::vector<Ev> events;
+  double prof_ms[4] = {0, 0, 0, 0};
+  int64_t prof_n[4] = {0, 0, 0, 0};
+  hipStream_t last_stream = nullptr;
+};
+
+namespace mdcell {
+
+// error plumbing (md_api.cpp)
+int set_error(int code, const std::string &msg);
+int check_hip(hipError_t e, const char *what);
+
+// profiling helpers (md_api.cpp)
+enum ProfGroup { PROF_PAIR = 0, PROF_BUILD = 1, PROF_STEP = 2, PROF_ADJ = 3 };
+void prof_begin(md_model *m, int group, hipStream_t s, hipEvent_t *a);
+void prof_end(md_model *m, int group, hipStream_t s, hipEvent_t a);
+
+// launchers
+int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat, const int32_t *comp, int64_t N,
+                 const double inv_h[3], hipStream_t s);
+int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o, hipStream_t s, int64_t *nblocks);
+int launch_reduce(md_model *m, int64_t nrows, int ncols, const double *rows, double *out, hipStream_t s);
+int launch_finish_forces(const double *sums, double *uw, int64_t *npairs, double *energies_row, hipStream_t s);
+int launch_leapfrog(md_model *m, double *pos, double *vel, double *quat, double *angmom, const int32_t *comp,
+                    int64_t N, const double box[3], double dt, const double *force, const double *torque,
+                    double *energies_row, hipStream_t s);
+int launch_adjoint(md_model *m, const md_cells *c, int precision, const AdjOut &o, hipStream_t s, int64_t *nblocks);
+int launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+int launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+int launch_scale_copy(const double *src, double *dst, int64_t n, double a, hipStream_t s);
+
+// number of pair-kernel blocks for a grid of ncell cells (a multiple of 8, see xcd_remap)
+inline int64_t pair_blocks(int64_t ncell) { return ((ncell + 7) / 8) * 8; }
+
+}  // namespace mdcell
+
+// Periodic wrap into [0, L): x - L floor(x / L), minus L once more if rounding left it at L.
+// The library is compiled without floating-point contraction, so this is one division, one
+// floor, one multiply and one subtraction, each correctly rounded.
+__device__ __forceinline__ double wrap1(double x, double L) {
+  double xw = x - L * floor(x / L);
+  if (xw >= L) xw -= L;
+  return xw;
+}
+
+// Blocks of one launch are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8),
+// each XCD with its own L2.  Give XCD k a contiguous run of cells so that neighbouring cells,
+// which read the same neighbour data, meet in one L2.  nblocks is a multiple of 8.
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+  const int per = nblocks >> 3;
+  return (b & 7) * per + (b >> 3);
+}

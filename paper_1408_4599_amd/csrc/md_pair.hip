@@ -1,0 +1,645 @@
+// Linked-cell pair kernels: forces, torques, energy and virial of rigid multi-centre molecules
+// (Sec. 2 interaction models; Sec. 3 linked cells, periodic boundaries, summation of forces and
+// torques per molecule).
+//
+// Work decomposition (one wavefront of 64 lanes per home cell):
+//   * the 27 cells around the home cell (edge >= r_c, so every partner inside the cutoff is
+//     there, Sec. 3) are staged into LDS with their periodic image shift already applied;
+//   * lanes are split into NI molecule lanes x NS = 64 / NI partner slices (NI = 16, 32 or 64
+//     from the home-cell occupancy), lane (i, s) scans staged partners s, s + NS, ...;
+//   * the COM cutoff test is done in FP64 with the exact expression
+//     fma(dz, dz, fma(dy, dy, dx * dx)) < r_c^2 on d = r_i - (r_j + shift), so the set of
+//     interacting pairs is the brute-force set bit for bit;
+//   * site-site arithmetic runs in R (float for MD_FP32, double for MD_FP64), per-molecule sums
+//     accumulate in FP64 and are reduced across the NS slices with cross-lane shuffles;
+//   * every home cell writes one row of block partials (energy, virial diagonal, pair count)
+//     which a deterministic two-stage reduction sums in a fixed order.
+// Every pair is evaluated from both ends (full shell), so no atomics are needed and results are
+// bitwise reproducible.  The pair work is VALU-bound (no dense contraction: no MFMA).
+
+#include "md_internal.h"
+
+namespace mdcell {
+namespace {
+
+// ---------------------------------------------------------------- arithmetic helpers
+// Reciprocal and reciprocal square root: the hardware estimate refined by Newton-Raphson
+// iterations (r <- r + r (1 - x r); y <- y + y (1 - x y^2) / 2), once in FP32, twice / three
+// times in FP64.
+template <typename R> __device__ __forceinline__ R rcp_nr(R x);
+template <> __device__ __forceinline__ float rcp_nr<float>(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  const float e = fmaf(-x, r, 1.0f);
+  return fmaf(r, e, r);
+}
+template <> __device__ __forceinline__ double rcp_nr<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+template <typename R> __device__ __forceinline__ R rsq_nr(R x);
+template <> __device__ __forceinline__ float rsq_nr<float>(float x) {
+  const float y = __builtin_amdgcn_rsqf(x);
+  const float h = x * y;
+  const float e = fmaf(-h, y, 1.0f);
+  return fmaf(0.5f * y, e, y);
+}
+template <> __device__ __forceinline__ double rsq_nr<double>(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double h = x * y;
+    const double e = fma(-h, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
+template <typename R> __device__ __forceinline__ void addto(double &a, R x) { a += (double)x; }
+
+// LJ force scalar fs = 24 eps s^6 (2 s^6 - 1) / r^2 (force on i = fs * r_ij), evaluated in R from
+// the FP64 squared distance.  FP32: one hardware reciprocal (1 ulp), no refinement -- the force
+// error budget is 1e-5 relative.  FP64: reciprocal refined by two Newton steps.
+template <typename R> __device__ __forceinline__ double lj_force_scalar(double r2, R eps24, R sig2);
+template <> __device__ __forceinline__ double lj_force_scalar<float>(double r2, float eps24, float sig2) {
+  const float ir2 = __builtin_amdgcn_rcpf((float)r2);
+  const float s2 = sig2 * ir2;
+  const float s6 = s2 * s2 * s2;
+  return (double)((eps24 * ir2) * (s6 * fmaf(2.0f, s6, -1.0f)));
+}
+template <> __device__ __forceinline__ double lj_force_scalar<double>(double r2, double eps24, double sig2) {
+  const double ir2 = rcp_nr<double>(r2);
+  const double s2 = sig2 * ir2;
+  const double s6 = s2 * s2 * s2;
+  return (eps24 * ir2) * (s6 * fma(2.0, s6, -1.0));
+}
+// 1 / r2 to FP64 accuracy: FP32 path starts from the FP32 hardware reciprocal (recomputed; the
+// compiler merges it with the one in lj_force_scalar) and takes one FP64 Newton step (2^-23 ->
+// ~2^-46 relative); FP64 path uses the twice-refined FP64 reciprocal.
+template <typename R> __device__ __forceinline__ double rcp_fp64_from(double r2);
+template <> __device__ __forceinline__ double rcp_fp64_from<float>(double r2) {
+  double r = (double)__builtin_amdgcn_rcpf((float)r2);
+  const double e = fma(-r2, r, 1.0);
+  return fma(r, e, r);
+}
+template <> __device__ __forceinline__ double rcp_fp64_from<double>(double r2) { return rcp_nr<double>(r2); }
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------- neighbour-cell table
+struct NbTable {
+  int off[28];   // exclusive prefix of the 27 cell counts (off[27] = total staged)
+  int start[27]; // first sorted slot of each neighbour cell
+  double sh[27][3];
+};
+
+// Stencil entry k = 0..26 is (dx, dy, dz) = (k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1); entry 13
+// is the home cell.  A neighbour index that leaves the grid wraps around, and the molecules of
+// the wrapped cell are seen through the image shift -L (from below) or +L (from above).
+__device__ __forceinline__ void build_nb(const CellsDev &c, int cell, NbTable &t) {
+  const int lane = threadIdx.x;
+  int cnt = 0;
+  if (lane < 27) {
+    const int cx = cell % c.nx, cy = (cell / c.nx) % c.ny, cz = cell / (c.nx * c.ny);
+    int x = cx + lane % 3 - 1, y = cy + (lane / 3) % 3 - 1, z = cz + lane / 9 - 1;
+    double shx = 0.0, shy = 0.0, shz = 0.0;
+    if (x < 0) x += c.nx, shx = -c.Lx;
+    else if (x >= c.nx) x -= c.nx, shx = c.Lx;
+    if (y < 0) y += c.ny, shy = -c.Ly;
+    else if (y >= c.ny) y -= c.ny, shy = c.Ly;
+    if (z < 0) z += c.nz, shz = -c.Lz;
+    else if (z >= c.nz) z -= c.nz, shz = c.Lz;
+    const int nc = (z * c.ny + y) * c.nx + x;
+    const int s = c.cell_start[nc];
+    cnt = c.cell_start[nc + 1] - s;
+    t.start[lane] = s;
+    t.sh[lane][0] = shx;
+    t.sh[lane][1] = shy;
+    t.sh[lane][2] = shz;
+  }
+  const int incl = wave_incl_scan(cnt);
+  if (lane < 27) t.off[lane] = incl - cnt;
+  if (lane == 26) t.off[27] = incl;
+}
+
+// Last stencil entry k with off[k] <= g (skips empty cells).
+__device__ __forceinline__ int find_nb(const int *off, int g) {
+  int lo = 0, hi = 27;
+#pragma unroll
+  for (int it = 0; it < 5; ++it) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- block partials
+__device__ __forceinline__ void write_partial(double *partial, double u, double wx, double wy, double wz, double n) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    u += __shfl_xor(u, o);
+    wx += __shfl_xor(wx, o);
+    wy += __shfl_xor(wy, o);
+    wz += __shfl_xor(wz, o);
+    n += __shfl_xor(n, o);
+  }
+  if (threadIdx.x == 0) {
+    double *p = partial + (int64_t)blockIdx.x * PARTIAL_COLS;
+    p[0] = u, p[1] = wx, p[2] = wy, p[3] = wz, p[4] = n;
+  }
+}
+
+// =====================================================================================
+// Single-site Lennard-Jones (LJ or LJTS, Sec. 2): the molecule is its one site.
+// =====================================================================================
+template <typename R, int CAP>
+__global__ __launch_bounds__(64) void k_pair_lj1(CellsDev c, LJPair p, double rc2, PairOut o) {
+  __shared__ double jx[CAP], jy[CAP], jz[CAP];
+  __shared__ NbTable nb;
+  const int lane = threadIdx.x;
+  const int cell = xcd_remap(blockIdx.x, gridDim.x);
+  double bu = 0.0, bwx = 0.0, bwy = 0.0, bwz = 0.0, bn = 0.0;
+  const int hs = cell < c.ncell ? c.cell_start[cell] : 0;
+  const int hn = cell < c.ncell ? c.cell_start[cell + 1] - hs : 0;
+  if (hn > 0) {
+    build_nb(c, cell, nb);
+    __syncthreads();
+    const int M = nb.off[27];
+    const int self0 = nb.off[13];
+    const int NI = hn <= 16 ? 16 : (hn <= 32 ? 32 : 64);
+    const int NS = 64 / NI;
+    const int il = lane & (NI - 1), sl = lane / NI;
+    const R eps24 = (R)p.eps24, sig2 = (R)p.sig2;
+    const double eps4d = p.eps4, sig2d = p.sig2;
+    for (int ic = 0; ic < hn; ic += 64) {
+      const int iloc = ic + il;
+      const bool act = iloc < hn;
+      double xi = 0.0, yi = 0.0, zi = 0.0;
+      if (act) xi = c.sx[hs + iloc], yi = c.sy[hs + iloc], zi = c.sz[hs + iloc];
+      double fx = 0.0, fy = 0.0, fz = 0.0, uu = 0.0, wx = 0.0, wy = 0.0, wz = 0.0;
+      int nn = 0;
+      for (int jc = 0; jc < M; jc += CAP) {
+        const int mj = min(CAP, M - jc);
+        __syncthreads();
+        for (int t = lane; t < mj; t += 64) {
+          const int g = jc + t;
+          const int k = find_nb(nb.off, g);
+          const int src = nb.start[k] + (g - nb.off[k]);
+          jx[t] = c.sx[src] + nb.sh[k][0];
+          jy[t] = c.sy[src] + nb.sh[k][1];
+          jz[t] = c.sz[src] + nb.sh[k][2];
+        }
+        __syncthreads();
+        if (act) {
+          const int self = self0 + iloc - jc;
+          for (int t = sl; t < mj; t += NS) {
+            const double dx = xi - jx[t], dy = yi - jy[t], dz = zi - jz[t];
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            if (r2 < rc2 && t != self) {
+              // force scalar in R; products with the exact FP64 separation and all sums in FP64
+              const double fs = lj_force_scalar<R>(r2, eps24, sig2);
+              const double gx = fs * dx, gy = fs * dy, gz = fs * dz;
+              fx += gx, fy += gy, fz += gz;
+              wx = fma(gx, dx, wx), wy = fma(gy, dy, wy), wz = fma(gz, dz, wz);
+              // pair energy in FP64 from the reciprocal refined to FP64 accuracy
+              const double ir2 = rcp_fp64_from<R>(r2);
+              const double s2 = sig2d * ir2;
+              const double s6 = s2 * s2 * s2;
+              uu = fma(eps4d * s6, s6 - 1.0, uu);  // LJTS shift: once per pair count, below
+              nn += 1;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int off = 16; off < 64; off <<= 1) {
+        if (off >= NI) {
+          fx += __shfl_xor(fx, off), fy += __shfl_xor(fy, off), fz += __shfl_xor(fz, off);
+          uu += __shfl_xor(uu, off);
+          wx += __shfl_xor(wx, off), wy += __shfl_xor(wy, off), wz += __shfl_xor(wz, off);
+          nn += __shfl_xor(nn, off);
+        }
+      }
+      if (sl == 0 && act) {
+        const int orig = c.perm[hs + iloc];
+        uu -= (double)nn * p.shift;
+        o.force[3 * orig] = fx, o.force[3 * orig + 1] = fy, o.force[3 * orig + 2] = fz;
+        if (o.torque) o.torque[3 * orig] = 0.0, o.torque[3 * orig + 1] = 0.0, o.torque[3 * orig + 2] = 0.0;
+        if (o.u_mol) o.u_mol[orig] = 0.5 * uu;
+        if (o.w_mol) o.w_mol[orig] = 0.5 * (wx + wy + wz);
+        if (o.nnb_mol) o.nnb_mol[orig] = nn;
+        bu += 0.5 * uu, bwx += 0.5 * wx, bwy += 0.5 * wy, bwz += 0.5 * wz, bn += (double)nn;
+      }
+    }
+  }
+  write_partial(o.partial, bu, bwx, bwy, bwz, bn);
+}
+
+// =====================================================================================
+// Multi-site molecules: LJ sites (Lorentz-Berthelot, optional shift) + point charges, point
+// dipoles, linear point quadrupoles (k_C = 1) + reaction field on dipole pairs.
+// =====================================================================================
+
+// Energy per unit moment product of one electrostatic site pair and its partial derivatives
+// with respect to r and the cosines c_i = e_a.rhat, c_j = e_b.rhat, c_ij = e_a.e_b (rhat points
+// from site b of molecule j to site a of molecule i).  ir = 1/r; krc3 = kappa / r_c^3.
+template <typename R> struct Unit {
+  R t, tr, ti, tj, tij;
+};
+
+template <int KA, int KB, typename R>
+__device__ __forceinline__ Unit<R> unit_terms(R ir, R ci, R cj, R cij, R krc3) {
+  Unit<R> u{0, 0, 0, 0, 0};
+  const R ir2 = ir * ir, ir3 = ir2 * ir, ir4 = ir3 * ir;
+  if constexpr (KA == KIND_CHG && KB == KIND_CHG) {
+    u.t = ir;
+    u.tr = -ir2;
+  } else if constexpr (KA == KIND_CHG && KB == KIND_DIP) {
+    u.t = cj * ir2;
+    u.tr = (R)-2 * cj * ir3;
+    u.tj = ir2;
+  } else if constexpr (KA == KIND_DIP && KB == KIND_CHG) {
+    u.t = -ci * ir2;
+    u.tr = (R)2 * ci * ir3;
+    u.ti = -ir2;
+  } else if constexpr (KA == KIND_CHG && KB == KIND_QUAD) {
+    u.t = (R)0.5 * fma((R)3 * cj, cj, (R)-1) * ir3;
+    u.tr = (R)-3 * u.t * ir;
+    u.tj = (R)3 * cj * ir3;
+  } else if constexpr (KA == KIND_QUAD && KB == KIND_CHG) {
+    u.t = (R)0.5 * fma((R)3 * ci, ci, (R)-1) * ir3;
+    u.tr = (R)-3 * u.t * ir;
+    u.ti = (R)3 * ci * ir3;
+  } else if constexpr (KA == KIND_DIP && KB == KIND_DIP) {
+    const R g = fma((R)-3 * ci, cj, cij);
+    u.t = fma(g, ir3, -krc3 * cij);
+    u.tr = (R)-3 * g * ir4;
+    u.ti = (R)-3 * cj * ir3;
+    u.tj = (R)-3 * ci * ir3;
+    u.tij = ir3 - krc3;
+  } else if constexpr (KA == KIND_DIP && KB == KIND_QUAD) {
+    const R p = (R)1.5 * ir4;
+    const R g = ci - (R)5 * ci * cj * cj + (R)2 * cj * cij;
+    u.t = p * g;
+    u.tr = (R)-4 * u.t * ir;
+    u.ti = p * fma((R)-5 * cj, cj, (R)1);
+    u.tj = p * fma((R)-10 * ci, cj, (R)2 * cij);
+    u.tij = p * (R)2 * cj;
+  } else if constexpr (KA == KIND_QUAD && KB == KIND_DIP) {
+    const R p = (R)-1.5 * ir4;
+    const R g = cj - (R)5 * cj * ci * ci + (R)2 * ci * cij;
+    u.t = p * g;
+    u.tr = (R)-4 * u.t * ir;
+    u.tj = p * fma((R)-5 * ci, ci, (R)1);
+    u.ti = p * fma((R)-10 * ci, cj, (R)2 * cij);
+    u.tij = p * (R)2 * ci;
+  } else {  // QUAD-QUAD
+    const R p = (R)0.75 * ir4 * ir;
+    const R s = fma((R)-5 * ci, cj, cij);
+    const R ci2 = ci * ci, cj2 = cj * cj;
+    u.t = p * ((R)1 - (R)5 * ci2 - (R)5 * cj2 - (R)15 * ci2 * cj2 + (R)2 * s * s);
+    u.tr = (R)-5 * u.t * ir;
+    u.ti = p * ((R)-10 * ci - (R)30 * ci * cj2 - (R)20 * cj * s);
+    u.tj = p * ((R)-10 * cj - (R)30 * cj * ci2 - (R)20 * ci * s);
+    u.tij = p * (R)4 * s;
+  }
+  return u;
+}
+
+template <typename R> __device__ __forceinline__ void cross_acc(R *T, const R *a, const R *f) {
+  T[0] += a[1] * f[2] - a[2] * f[1];
+  T[1] += a[2] * f[0] - a[0] * f[2];
+  T[2] += a[0] * f[1] - a[1] * f[0];
+}
+
+// Accumulators of one molecule pair (seen from molecule i).
+template <typename R> struct PairAcc {
+  R F[3], T[3], u;
+};
+
+// One electrostatic site pair: site a of i (offset oa, axis ea) and site b of j (ob, eb).
+template <int KA, int KB, typename R>
+__device__ __forceinline__ void elec_site(R pm, const R *oa, const R *ea, const R *ob, const R *eb, R dx, R dy, R dz,
+                                          R krc3, PairAcc<R> &acc) {
+  const R rx = dx + oa[0] - ob[0], ry = dy + oa[1] - ob[1], rz = dz + oa[2] - ob[2];
+  const R r2 = fma(rz, rz, fma(ry, ry, rx * rx));
+  const R ir = rsq_nr<R>(r2);
+  const R rh[3] = {rx * ir, ry * ir, rz * ir};
+  const R ci = (KA != KIND_CHG) ? fma(ea[2], rh[2], fma(ea[1], rh[1], ea[0] * rh[0])) : (R)0;
+  const R cj = (KB != KIND_CHG) ? fma(eb[2], rh[2], fma(eb[1], rh[1], eb[0] * rh[0])) : (R)0;
+  const R cij = (KA != KIND_CHG && KB != KIND_CHG) ? fma(ea[2], eb[2], fma(ea[1], eb[1], ea[0] * eb[0])) : (R)0;
+  const Unit<R> t = unit_terms<KA, KB, R>(ir, ci, cj, cij, krc3);
+  R f[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    R g = t.tr * rh[k];
+    if constexpr (KA != KIND_CHG) g += t.ti * (ea[k] - ci * rh[k]) * ir;
+    if constexpr (KB != KIND_CHG) g += t.tj * (eb[k] - cj * rh[k]) * ir;
+    f[k] = -pm * g;
+  }
+  acc.F[0] += f[0], acc.F[1] += f[1], acc.F[2] += f[2];
+  cross_acc(acc.T, oa, f);
+  if constexpr (KA != KIND_CHG) {
+    R ga[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ga[k] = t.ti * rh[k];
+      if constexpr (KB != KIND_CHG) ga[k] += t.tij * eb[k];
+      ga[k] *= -pm;
+    }
+    cross_acc(acc.T, ea, ga);  // tau -= e_a x dU/de_a
+  }
+  acc.u += pm * t.t;
+}
+
+// Slot layout of the per-molecule vectors for shape (SL, SC, SD, SQ).
+template <int SL, int SC, int SD, int SQ> struct Slots {
+  static constexpr int lj = 0, chg = SL, dip = SL + SC, dipax = SL + SC + SD, quad = SL + SC + 2 * SD,
+                       quadax = SL + SC + 2 * SD + SQ, nv = SL + SC + 2 * SD + 2 * SQ;
+};
+
+template <int KA, int KB> struct KindSlots;
+
+// All electrostatic site pairs of kinds (KA on i, KB on j).
+template <int KA, int KB, int SL, int SC, int SD, int SQ, bool MIX, typename R>
+__device__ __forceinline__ void elec_group(const CompDev &A, const CompDev &B, const R (*vi)[3], const R *vj,
+                                           R dx, R dy, R dz, R krc3, PairAcc<R> &acc) {
+  using S = Slots<SL, SC, SD, SQ>;
+  constexpr int NA = KA == KIND_CHG ? SC : (KA == KIND_DIP ? SD : SQ);
+  constexpr int NB = KB == KIND_CHG ? SC : (KB == KIND_DIP ? SD : SQ);
+  constexpr int OA = KA == KIND_CHG ? S::chg : (KA == KIND_DIP ? S::dip : S::quad);
+  constexpr int OB = KB == KIND_CHG ? S::chg : (KB == KIND_DIP ? S::dip : S::quad);
+  constexpr int EA = KA == KIND_DIP ? S::dipax : (KA == KIND_QUAD ? S::quadax : 0);
+  constexpr int EB = KB == KIND_DIP ? S::dipax : (KB == KIND_QUAD ? S::quadax : 0);
+  const int na = MIX ? (KA == KIND_CHG ? A.n_chg : (KA == KIND_DIP ? A.n_dip : A.n_quad)) : NA;
+  const int nb = MIX ? (KB == KIND_CHG ? B.n_chg : (KB == KIND_DIP ? B.n_dip : B.n_quad)) : NB;
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    if (a >= na) break;
+    const R ma = (R)(KA == KIND_CHG ? A.chg_q[a] : (KA == KIND_DIP ? A.dip_mu[a] : A.quad_Q[a]));
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (b >= nb) break;
+      const R mb = (R)(KB == KIND_CHG ? B.chg_q[b] : (KB == KIND_DIP ? B.dip_mu[b] : B.quad_Q[b]));
+      elec_site<KA, KB, R>(ma * mb, vi[OA + a], vi[EA + a], vj + 3 * (OB + b), vj + 3 * (EB + b), dx, dy, dz,
+                           krc3, acc);
+    }
+  }
+}
+
+template <int SL, int SC, int SD, int SQ, bool MIX, typename R>
+__device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci, int cj, const R (*vi)[3],
+                                         const R *vj, R dx, R dy, R dz, PairAcc<R> &acc) {
+  const CompDev &A = md->comp[ci];
+  const CompDev &B = md->comp[cj];
+  const int nla = MIX ? A.n_lj : SL, nlb = MIX ? B.n_lj : SL;
+#pragma unroll
+  for (int a = 0; a < SL; ++a) {
+    if (a >= nla) break;
+#pragma unroll
+    for (int b = 0; b < SL; ++b) {
+      if (b >= nlb) break;
+      const LJPair &p = md->lj[ci][cj][a][b];
+      const R *ob = vj + 3 * b;
+      const R rx = dx + vi[a][0] - ob[0], ry = dy + vi[a][1] - ob[1], rz = dz + vi[a][2] - ob[2];
+      const R r2 = fma(rz, rz, fma(ry, ry, rx * rx));
+      const R ir2 = rcp_nr<R>(r2);
+      const R s2 = (R)p.sig2 * ir2;
+      const R s6 = s2 * s2 * s2;
+      acc.u += ((R)p.eps4 * s6) * (s6 - (R)1);  // shift summed per molecule pair in FP64
+      const R fs = ((R)p.eps24 * ir2) * (s6 * fma((R)2, s6, (R)-1));
+      const R f[3] = {fs * rx, fs * ry, fs * rz};
+      acc.F[0] += f[0], acc.F[1] += f[1], acc.F[2] += f[2];
+      cross_acc(acc.T, vi[a], f);
+    }
+  }
+  if constexpr (SC + SD + SQ > 0) {
+    const R krc3 = (R)md->kappa_rc3;
+    if constexpr (SC > 0) {
+      elec_group<KIND_CHG, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+      if constexpr (SD > 0) {
+        elec_group<KIND_CHG, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+        elec_group<KIND_DIP, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+      }
+      if constexpr (SQ > 0) {
+        elec_group<KIND_CHG, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+        elec_group<KIND_QUAD, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+      }
+    }
+    if constexpr (SD > 0) {
+      elec_group<KIND_DIP, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+      if constexpr (SQ > 0) {
+        elec_group<KIND_DIP, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+        elec_group<KIND_QUAD, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+      }
+    }
+    if constexpr (SQ > 0) elec_group<KIND_QUAD, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+  }
+}
+
+template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP>
+__global__ __launch_bounds__(64) void k_pair_ms(CellsDev c, const ModelDev *__restrict__ md, double rc2, PairOut o) {
+  constexpr int NV = Slots<SL, SC, SD, SQ>::nv;
+  __shared__ double jx[CAP], jy[CAP], jz[CAP];
+  __shared__ R jv[CAP][NV * 3];
+  __shared__ int jc_[MIX ? CAP : 1];
+  __shared__ NbTable nb;
+  const int lane = threadIdx.x;
+  const int cell = xcd_remap(blockIdx.x, gridDim.x);
+  double bu = 0.0, bwx = 0.0, bwy = 0.0, bwz = 0.0, bn = 0.0;
+  const int hs = cell < c.ncell ? c.cell_start[cell] : 0;
+  const int hn = cell < c.ncell ? c.cell_start[cell + 1] - hs : 0;
+  if (hn > 0) {
+    build_nb(c, cell, nb);
+    __syncthreads();
+    const int M = nb.off[27];
+    const int self0 = nb.off[13];
+    const int NI = hn <= 16 ? 16 : (hn <= 32 ? 32 : 64);
+    const int NS = 64 / NI;
+    const int il = lane & (NI - 1), sl = lane / NI;
+    for (int ic = 0; ic < hn; ic += 64) {
+      const int iloc = ic + il;
+      const bool act = iloc < hn;
+      double xi = 0.0, yi = 0.0, zi = 0.0;
+      R vi[NV][3];
+      int ci = 0;
+      if (act) {
+        const int s = hs + iloc;
+        xi = c.sx[s], yi = c.sy[s], zi = c.sz[s];
+        if (MIX) ci = c.scomp[s];
+        const double *v = c.svec + (int64_t)s * NV * 3;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) vi[k][0] = (R)v[3 * k], vi[k][1] = (R)v[3 * k + 1], vi[k][2] = (R)v[3 * k + 2];
+      } else {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) vi[k][0] = vi[k][1] = vi[k][2] = (R)0;
+      }
+      double fx = 0.0, fy = 0.0, fz = 0.0, tx = 0.0, ty = 0.0, tz = 0.0, uu = 0.0, wx = 0.0, wy = 0.0, wz = 0.0;
+      double ush = 0.0;  // LJTS shifts of the interacting molecule pairs (mixtures)
+      int nn = 0;
+      for (int jc = 0; jc < M; jc += CAP) {
+        const int mj = min(CAP, M - jc);
+        __syncthreads();
+        for (int t = lane; t < mj; t += 64) {
+          const int g = jc + t;
+          const int k = find_nb(nb.off, g);
+          const int src = nb.start[k] + (g - nb.off[k]);
+          jx[t] = c.sx[src] + nb.sh[k][0];
+          jy[t] = c.sy[src] + nb.sh[k][1];
+          jz[t] = c.sz[src] + nb.sh[k][2];
+          if (MIX) jc_[t] = c.scomp[src];  // written (clamped to [0, ncomp)) by the gather
+          const double *v = c.svec + (int64_t)src * NV * 3;
+#pragma unroll
+          for (int q = 0; q < NV * 3; ++q) jv[t][q] = (R)v[q];
+        }
+        __syncthreads();
+        if (act) {
+          const int self = self0 + iloc - jc;
+          for (int t = sl; t < mj; t += NS) {
+            const double dx = xi - jx[t], dy = yi - jy[t], dz = zi - jz[t];
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            if (r2 < rc2 && t != self) {
+              PairAcc<R> acc{{0, 0, 0}, {0, 0, 0}, 0};
+              const int cj = MIX ? jc_[t] : 0;
+              mol_pair<SL, SC, SD, SQ, MIX, R>(md, ci, cj, vi, jv[t], (R)dx, (R)dy, (R)dz, acc);
+              addto(fx, acc.F[0]), addto(fy, acc.F[1]), addto(fz, acc.F[2]);
+              addto(tx, acc.T[0]), addto(ty, acc.T[1]), addto(tz, acc.T[2]);
+              addto(uu, acc.u);
+              wx = fma(dx, (double)acc.F[0], wx);
+              wy = fma(dy, (double)acc.F[1], wy);
+              wz = fma(dz, (double)acc.F[2], wz);
+              if (MIX) ush += md->shift_sum[ci][cj];
+              nn += 1;
+            }
+          }
+        }
+      }
+      uu -= MIX ? ush : (double)nn * md->shift_sum[0][0];
+#pragma unroll
+      for (int off = 16; off < 64; off <<= 1) {
+        if (off >= NI) {
+          fx += __shfl_xor(fx, off), fy += __shfl_xor(fy, off), fz += __shfl_xor(fz, off);
+          tx += __shfl_xor(tx, off), ty += __shfl_xor(ty, off), tz += __shfl_xor(tz, off);
+          uu += __shfl_xor(uu, off);
+          wx += __shfl_xor(wx, off), wy += __shfl_xor(wy, off), wz += __shfl_xor(wz, off);
+          nn += __shfl_xor(nn, off);
+        }
+      }
+      if (sl == 0 && act) {
+        const int orig = c.perm[hs + iloc];
+        o.force[3 * orig] = fx, o.force[3 * orig + 1] = fy, o.force[3 * orig + 2] = fz;
+        if (o.torque) o.torque[3 * orig] = tx, o.torque[3 * orig + 1] = ty, o.torque[3 * orig + 2] = tz;
+        if (o.u_mol) o.u_mol[orig] = 0.5 * uu;
+        if (o.w_mol) o.w_mol[orig] = 0.5 * (wx + wy + wz);
+        if (o.nnb_mol) o.nnb_mol[orig] = nn;
+        bu += 0.5 * uu, bwx += 0.5 * wx, bwy += 0.5 * wy, bwz += 0.5 * wz, bn += (double)nn;
+      }
+    }
+  }
+  write_partial(o.partial, bu, bwx, bwy, bwz, bn);
+}
+
+// ---------------------------------------------------------------- deterministic reductions
+constexpr int RED_THREADS = 256;
+constexpr int RED_BLOCKS = 256;
+constexpr int RED_MAXCOLS = 256;
+
+// Stage 1: block b sums rows [b * chunk, (b + 1) * chunk) of a [nrows][ncols] table, thread t
+// taking rows t, t + 256, ... in order, then a fixed LDS tree.  Stage 2 (nblocks = 1) repeats
+// on the per-block results.  The summation order never depends on timing.
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_cols(const double *rows, int64_t nrows, int ncols,
+                                                             int64_t chunk, double *out) {
+  __shared__ double sh[RED_THREADS];
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = min(nrows, r0 + chunk);
+  for (int col = 0; col < ncols; ++col) {
+    double s = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += RED_THREADS) s += rows[r * ncols + col];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * ncols + col] = sh[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_finish_forces(const double *s, double *uw, int64_t *npairs, double *erow) {
+  if (threadIdx.x != 0) return;
+  const double U = s[0], W = s[1] + s[2] + s[3];
+  uw[0] = U, uw[1] = W, uw[2] = s[1], uw[3] = s[2], uw[4] = s[3];
+  if (npairs) *npairs = (int64_t)(s[4] * 0.5);
+  if (erow) erow[0] = U, erow[3] = W;
+}
+
+template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP>
+int launch_ms(const CellsDev &cd, const md_model *m, const PairOut &o, int64_t nb, hipStream_t s) {
+  k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, m->host.rc2, o);
+  return check_hip(hipGetLastError(), "k_pair_ms");
+}
+
+}  // namespace
+
+CellsDev cells_dev(const md_cells *c) {
+  CellsDev d;
+  d.cell_start = c->start;
+  d.perm = c->perm;
+  d.scomp = c->scomp;
+  d.sx = c->sx, d.sy = c->sy, d.sz = c->sz;
+  d.svec = c->svec;
+  d.nx = c->nc[0], d.ny = c->nc[1], d.nz = c->nc[2];
+  d.ncell = (int32_t)c->ncell;
+  d.nvec = c->nvec;
+  d.Lx = c->box[0], d.Ly = c->box[1], d.Lz = c->box[2];
+  return d;
+}
+
+int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o, hipStream_t s, int64_t *nblocks) {
+  const CellsDev cd = cells_dev(c);
+  const int64_t nb = pair_blocks(c->ncell);
+  *nblocks = nb;
+  const bool f32 = precision == MD_FP32;
+  if (m->single_site) {
+    const LJPair p = m->host.lj[0][0][0][0];
+    if (f32) k_pair_lj1<float, 512><<<(unsigned)nb, 64, 0, s>>>(cd, p, m->host.rc2, o);
+    else k_pair_lj1<double, 512><<<(unsigned)nb, 64, 0, s>>>(cd, p, m->host.rc2, o);
+    return check_hip(hipGetLastError(), "k_pair_lj1");
+  }
+  const Shape &S = m->shape;
+  if (m->fixed_shape && S.lj == 2 && S.chg == 0 && S.dip == 0 && S.quad == 1)
+    return f32 ? launch_ms<float, 2, 0, 0, 1, false, 256>(cd, m, o, nb, s)
+               : launch_ms<double, 2, 0, 0, 1, false, 256>(cd, m, o, nb, s);
+  if (m->fixed_shape && S.lj == 3 && S.chg == 0 && S.dip == 1 && S.quad == 0)
+    return f32 ? launch_ms<float, 3, 0, 1, 0, false, 256>(cd, m, o, nb, s)
+               : launch_ms<double, 3, 0, 1, 0, false, 256>(cd, m, o, nb, s);
+  return f32 ? launch_ms<float, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64>(cd, m, o, nb, s)
+             : launch_ms<double, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64>(cd, m, o, nb, s);
+}
+
+int launch_reduce(md_model *m, int64_t nrows, int ncols, const double *rows, double *out, hipStream_t s) {
+  if (ncols > RED_MAXCOLS) return set_error(MD_EINVAL, "reduction too wide");
+  const int64_t chunk = (nrows + RED_BLOCKS - 1) / RED_BLOCKS;
+  k_reduce_cols<<<RED_BLOCKS, RED_THREADS, 0, s>>>(rows, nrows, ncols, chunk > 0 ? chunk : 1, m->red2);
+  k_reduce_cols<<<1, RED_THREADS, 0, s>>>(m->red2, RED_BLOCKS, ncols, RED_BLOCKS, out);
+  return check_hip(hipGetLastError(), "k_reduce_cols");
+}
+
+int launch_finish_forces(const double *sums, double *uw, int64_t *npairs, double *erow, hipStream_t s) {
+  k_finish_forces<<<1, 64, 0, s>>>(sums, uw, npairs, erow);
+  return check_hip(hipGetLastError(), "k_finish_forces");
+}
+
+}  // namespace mdcell

@@ -1,0 +1,355 @@
+"""ctypes binding of libmdcell (include/md.h).  Argument marshalling only: every step of the
+force path runs in the library's HIP kernels.  PyTorch supplies device memory (CUDA tensors on
+ROCm) and the current stream.  There is no CPU fallback: without the built library or a GPU every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmdcell.so")
+
+MD_OK, MD_EINVAL, MD_EBOX, MD_ECOMP, MD_ENONFINITE, MD_EHIP, MD_ENOMEM, MD_EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
+MD_LJ_SHIFT, MD_CHECK = 0x1, 0x2
+MD_FP64, MD_FP32 = 0, 1
+PRECISION = {"fp64": MD_FP64, "fp32": MD_FP32, MD_FP64: MD_FP64, MD_FP32: MD_FP32}
+MAX_COMP, MAX_LJ, MAX_CHG, MAX_DIP, MAX_QUAD = 4, 4, 4, 2, 2
+
+
+class MDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libmdcell error {code}: {msg}")
+        self.code = code
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_lp = ctypes.POINTER(ctypes.c_int64)
+
+
+class ComponentDesc(ctypes.Structure):
+    _fields_ = [("n_lj", ctypes.c_int32), ("n_chg", ctypes.c_int32), ("n_dip", ctypes.c_int32),
+                ("n_quad", ctypes.c_int32), ("lj_pos", _dp), ("lj_eps", _dp), ("lj_sigma", _dp),
+                ("chg_pos", _dp), ("chg_q", _dp), ("dip_pos", _dp), ("dip_dir", _dp), ("dip_mu", _dp),
+                ("quad_pos", _dp), ("quad_dir", _dp), ("quad_Q", _dp), ("mass", ctypes.c_double),
+                ("inertia", ctypes.c_double * 3)]
+
+
+class CellsInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("ncell", ctypes.c_int64), ("nc", ctypes.c_int32 * 3),
+                ("box", ctypes.c_double * 3), ("cell_of", ctypes.c_void_p), ("cell_start", ctypes.c_void_p),
+                ("perm", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmdcell.so (built in-tree by ``paper_1408_4599_amd.build``); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libmdcell.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp = ctypes.c_void_p
+    L.md_last_error.restype = ctypes.c_char_p
+    L.md_last_error.argtypes = []
+    L.md_model_create.argtypes = [ctypes.POINTER(ComponentDesc), ctypes.c_int32, _dp, _dp, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_uint32, ctypes.POINTER(vp)]
+    L.md_model_destroy.argtypes = [vp]
+    L.md_param_count.argtypes = [vp]
+    L.md_param_count.restype = ctypes.c_int64
+    L.md_cells_create.argtypes = [ctypes.POINTER(vp)]
+    L.md_cells_destroy.argtypes = [vp]
+    L.md_cells_view.argtypes = [vp, ctypes.POINTER(CellsInfo)]
+    L.md_build_cells.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, _dp, vp]
+    L.md_forces.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.md_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int64, _dp, ctypes.c_double, ctypes.c_int64,
+                          ctypes.c_int, vp, vp]
+    L.md_forces_adjoint.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp, vp, vp, vp]
+    L.md_status.argtypes = [vp, _ip]
+    L.md_profile.argtypes = [vp, ctypes.c_int]
+    L.md_profile_read.argtypes = [vp, ctypes.c_char_p, _dp, _lp]
+    for name in ("md_model_create", "md_model_destroy", "md_cells_create", "md_cells_destroy", "md_cells_view",
+                 "md_build_cells", "md_forces", "md_step", "md_forces_adjoint", "md_status", "md_profile",
+                 "md_profile_read"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != MD_OK:
+        raise MDError(rc, lib().md_last_error().decode(errors="replace"))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (ROCm) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _arr(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64).reshape(-1))
+    return a
+
+
+class Model:
+    """A molecule model (component site tables, mixing, cutoff, reaction field) on the device.
+    Built from the model dictionaries of ``workloads``."""
+
+    def __init__(self, model: dict, check: bool = False):
+        comps = model["components"]
+        nc = len(comps)
+        descs = (ComponentDesc * nc)()
+        self._keep = []
+        for d, comp in zip(descs, comps):
+            by = {k: [s for s in comp["sites"] if s["kind"] == k] for k in ("lj", "charge", "dipole", "quadrupole")}
+            d.n_lj, d.n_chg, d.n_dip, d.n_quad = (len(by[k]) for k in ("lj", "charge", "dipole", "quadrupole"))
+
+            def put(vals):
+                a = _arr(vals) if len(vals) else np.zeros(1)
+                self._keep.append(a)
+                return a.ctypes.data_as(_dp)
+
+            d.lj_pos = put([s["pos"] for s in by["lj"]])
+            d.lj_eps = put([s["eps"] for s in by["lj"]])
+            d.lj_sigma = put([s["sigma"] for s in by["lj"]])
+            d.chg_pos = put([s["pos"] for s in by["charge"]])
+            d.chg_q = put([s["q"] for s in by["charge"]])
+            d.dip_pos = put([s["pos"] for s in by["dipole"]])
+            d.dip_dir = put([s["dir"] for s in by["dipole"]])
+            d.dip_mu = put([s["mu"] for s in by["dipole"]])
+            d.quad_pos = put([s["pos"] for s in by["quadrupole"]])
+            d.quad_dir = put([s["dir"] for s in by["quadrupole"]])
+            d.quad_Q = put([s["Q"] for s in by["quadrupole"]])
+            d.mass = float(comp["mass"])
+            for k in range(3):
+                d.inertia[k] = float(comp["inertia"][k])
+        xi = None if model.get("xi") is None else _arr(model["xi"])
+        eta = None if model.get("eta") is None else _arr(model["eta"])
+        flags = (MD_LJ_SHIFT if model.get("lj_shift") else 0) | (MD_CHECK if check else 0)
+        h = ctypes.c_void_p()
+        _check(lib().md_model_create(descs, nc, None if xi is None else xi.ctypes.data_as(_dp),
+                                     None if eta is None else eta.ctypes.data_as(_dp), float(model["rc"]),
+                                     float(model.get("eps_rf", math.inf)), flags, ctypes.byref(h)))
+        self.handle = h
+        self.model = model
+        self.ncomp = nc
+        self.single_site = (nc == 1 and len(comps[0]["sites"]) == 1 and comps[0]["sites"][0]["kind"] == "lj"
+                            and all(v == 0 for v in comps[0]["sites"][0]["pos"]))
+        self.nparam = int(lib().md_param_count(h))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().md_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def status(self) -> int:
+        v = ctypes.c_int32(0)
+        _check(lib().md_status(self.handle, ctypes.byref(v)))
+        return int(v.value)
+
+    def profile(self, enable: bool):
+        _check(lib().md_profile(self.handle, int(enable)))
+
+    def profile_read(self, group: str):
+        ms = ctypes.c_double(0)
+        n = ctypes.c_int64(0)
+        _check(lib().md_profile_read(self.handle, group.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
+
+    def param_layout(self):
+        """List of (component, kind, index, names) in the order of md_forces_adjoint's dparams."""
+        out = []
+        for c, comp in enumerate(self.model["components"]):
+            for kind, names in (("lj", ("eps", "sigma", "x", "y", "z")), ("charge", ("q", "x", "y", "z")),
+                                ("dipole", ("mu", "x", "y", "z")), ("quadrupole", ("Q", "x", "y", "z"))):
+                for i, _ in enumerate([s for s in comp["sites"] if s["kind"] == kind]):
+                    out.append((c, kind, i, names))
+        return out
+
+
+class Cells:
+    """A linked-cell grid with molecules sorted into it (library-owned device buffers)."""
+
+    def __init__(self):
+        h = ctypes.c_void_p()
+        _check(lib().md_cells_create(ctypes.byref(h)))
+        self.handle = h
+        self.N = 0
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().md_cells_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def view(self):
+        """Device copies of cell_of [N], cell_start [ncell+1], perm [N] (int32 CUDA tensors), plus
+        the grid shape."""
+        info = CellsInfo()
+        _check(lib().md_cells_view(self.handle, ctypes.byref(info)))
+        N, nc = int(info.N), int(info.ncell)
+
+        def copy(ptr, n):
+            out = torch.empty(n, dtype=torch.int32, device="cuda")
+            _hip_copy(out.data_ptr(), ptr, 4 * n)
+            return out
+
+        return {"N": N, "ncell": nc, "nc": tuple(info.nc), "box": tuple(info.box),
+                "cell_of": copy(info.cell_of, N), "cell_start": copy(info.cell_start, nc + 1),
+                "perm": copy(info.perm, N)}
+
+
+_hiprt = None
+
+
+def _hip_copy(dst, src, nbytes):
+    """Device-to-device copy on the current stream through the HIP runtime (plumbing only)."""
+    global _hiprt
+    if _hiprt is None:
+        _hiprt = ctypes.CDLL("libamdhip64.so")
+        _hiprt.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                          ctypes.c_void_p]
+        _hiprt.hipMemcpyAsync.restype = ctypes.c_int
+    err = _hiprt.hipMemcpyAsync(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 3, _stream())
+    if err != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed ({err})")
+
+
+def build_cells(model: Model, cells: Cells, pos, quat, comp, box):
+    N = pos.shape[0]
+    _need(pos, torch.float64, (N, 3), "pos")
+    if quat is not None:
+        _need(quat, torch.float64, (N, 4), "quat")
+    if comp is not None:
+        _need(comp, torch.int32, (N,), "comp")
+    boxa = _arr(box)
+    _check(lib().md_build_cells(model.handle, cells.handle, _ptr(pos), _ptr(quat), _ptr(comp), N,
+                                boxa.ctypes.data_as(_dp), _stream()))
+    cells.N = N
+
+
+def forces(model: Model, cells: Cells, precision="fp64", torque=True, per_molecule=True):
+    """Returns dict of CUDA tensors: force [N,3], torque [N,3] (if requested), u_mol, w_mol,
+    nnb (if per_molecule), uw [5] = (U, W, Wxx, Wyy, Wzz), npairs [1]."""
+    N = cells.N
+    dev = "cuda"
+    out = {"force": torch.empty((N, 3), dtype=torch.float64, device=dev),
+           "uw": torch.empty(5, dtype=torch.float64, device=dev),
+           "npairs": torch.empty(1, dtype=torch.int64, device=dev)}
+    if torque:
+        out["torque"] = torch.empty((N, 3), dtype=torch.float64, device=dev)
+    if per_molecule:
+        out["u_mol"] = torch.empty(N, dtype=torch.float64, device=dev)
+        out["w_mol"] = torch.empty(N, dtype=torch.float64, device=dev)
+        out["nnb"] = torch.empty(N, dtype=torch.int32, device=dev)
+    forces_into(model, cells, precision, out)
+    return out
+
+
+def forces_into(model: Model, cells: Cells, precision, out: dict):
+    """md_forces into preallocated tensors (keys as ``forces``; optional ones may be absent)."""
+    _check(lib().md_forces(model.handle, cells.handle, PRECISION[precision], _ptr(out["force"]),
+                           _ptr(out.get("torque")), _ptr(out.get("u_mol")), _ptr(out.get("w_mol")),
+                           _ptr(out.get("nnb")), _ptr(out["uw"]), _ptr(out.get("npairs")), _stream()))
+
+
+def step(model: Model, cells: Cells, pos, vel, quat, angmom, comp, box, dt, nsteps, precision="fp64",
+         energies=None):
+    """nsteps leapfrog steps in place on (pos, vel, quat, angmom); returns energies [nsteps, 4]
+    (U, K_trans, K_rot, W) as a CUDA tensor."""
+    N = pos.shape[0]
+    _need(pos, torch.float64, (N, 3), "pos")
+    _need(vel, torch.float64, (N, 3), "vel")
+    if quat is not None:
+        _need(quat, torch.float64, (N, 4), "quat")
+        _need(angmom, torch.float64, (N, 3), "angmom")
+    if comp is not None:
+        _need(comp, torch.int32, (N,), "comp")
+    if energies is None:
+        energies = torch.empty((max(1, nsteps), 4), dtype=torch.float64, device="cuda")
+    boxa = _arr(box)
+    _check(lib().md_step(model.handle, cells.handle, _ptr(pos), _ptr(vel), _ptr(quat), _ptr(angmom), _ptr(comp), N,
+                         boxa.ctypes.data_as(_dp), float(dt), int(nsteps), PRECISION[precision], _ptr(energies),
+                         _stream()))
+    cells.N = N
+    return energies[:nsteps]
+
+
+def forces_adjoint(model: Model, cells: Cells, precision="fp64", gU=1.0, want_quat=True, want_params=True):
+    """gU * dU/d(pos, quat, parameters) by the recomputing adjoint kernel."""
+    N = cells.N
+    out = {"dpos": torch.empty((N, 3), dtype=torch.float64, device="cuda")}
+    out["dquat"] = torch.empty((N, 4), dtype=torch.float64, device="cuda") if want_quat else None
+    out["dparams"] = (torch.empty(max(1, model.nparam), dtype=torch.float64, device="cuda")
+                      if (want_params and model.nparam > 0) else None)
+    _check(lib().md_forces_adjoint(model.handle, cells.handle, PRECISION[precision], float(gU), _ptr(out["dpos"]),
+                                   _ptr(out["dquat"]), _ptr(out["dparams"]), _stream()))
+    return out
+
+
+class EnergyFn(torch.autograd.Function):
+    """U(pos, quat) as a differentiable FP64 scalar.  Forward runs md_build_cells + md_forces;
+    backward re-traverses the cells with md_forces_adjoint (recomputation, no stored pair list).
+    Parameter gradients are available through ``forces_adjoint`` (the model tables live in the
+    library, not in torch tensors)."""
+
+    @staticmethod
+    def forward(ctx, pos, quat, model, cells, box, comp, precision):
+        build_cells(model, cells, pos.detach().contiguous(), None if quat is None else quat.detach().contiguous(),
+                    comp, box)
+        r = forces(model, cells, precision, torque=False, per_molecule=False)
+        ctx.model, ctx.cells, ctx.precision = model, cells, precision
+        ctx.has_quat = quat is not None
+        ctx.save_for_backward(pos, quat if quat is not None else torch.empty(0, device=pos.device), comp if comp is not None else torch.empty(0, device=pos.device))
+        ctx.box = box
+        return r["uw"][0].clone()
+
+    @staticmethod
+    def backward(ctx, gU):
+        pos, quat, comp = ctx.saved_tensors
+        quat_t = quat if ctx.has_quat else None
+        comp_t = comp if comp.numel() else None
+        build_cells(ctx.model, ctx.cells, pos.detach().contiguous(),
+                    None if quat_t is None else quat_t.detach().contiguous(), comp_t, ctx.box)
+        g = forces_adjoint(ctx.model, ctx.cells, ctx.precision, float(gU.item()), want_quat=ctx.has_quat,
+                           want_params=False)
+        return g["dpos"], (g["dquat"] if ctx.has_quat else None), None, None, None, None, None
+
+
+def energy(pos, quat, model, cells, box, comp=None, precision="fp64"):
+    return EnergyFn.apply(pos, quat, model, cells, box, comp, precision)

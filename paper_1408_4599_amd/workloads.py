@@ -292,21 +292,35 @@ def mixture_small(N=1000, seed=21):
 
 
 def random_gas(N, box, model, seed=31, T=1.0, name="random_gas", dmin=0.0):
-    """Uniform random COMs (uneven cell occupancy, empty cells), optional minimum separation."""
+    """Uniform random COMs (uneven cell occupancy, empty cells), optionally with no two
+    molecules closer than dmin (random sequential addition on a periodic grid hash; keep
+    N dmin^3 / V well below ~1.5, the jamming density of that process)."""
     rng = rng_for(seed)
     box = np.asarray(box, dtype=np.float64)
     if dmin <= 0.0:
         pos = rng.uniform(size=(N, 3)) * box
     else:
-        from scipy.spatial import cKDTree
+        if N * dmin ** 3 / np.prod(box) > 1.0:
+            raise ValueError("random_gas: too dense for the requested minimum separation")
+        ng = np.maximum(np.floor(box / dmin).astype(np.int64), 1)
+        edge = box / ng
+        grid = {}
         pts = []
         while len(pts) < N:
-            c = rng.uniform(size=3) * box
-            if pts:
-                t = cKDTree(np.asarray(pts), boxsize=box)
-                if t.query_ball_point(c, dmin):
-                    continue
-            pts.append(c)
+            p = rng.uniform(size=3) * box
+            key = np.minimum((p // edge).astype(np.int64), ng - 1)
+            ok = True
+            for dx in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dz in (-1, 0, 1):
+                        for q in grid.get(((key[0] + dx) % ng[0], (key[1] + dy) % ng[1], (key[2] + dz) % ng[2]), ()):
+                            d = p - q
+                            d -= box * np.round(d / box)
+                            if d @ d < dmin * dmin:
+                                ok = False
+            if ok:
+                grid.setdefault((key[0], key[1], key[2]), []).append(p)
+                pts.append(p)
         pos = np.asarray(pts)
     return _system(name, model, pos, box, T, rng, 0.001, 10)
 

@@ -1,0 +1,32 @@
+"""Helpers for the GPU tests: move generator arrays onto the device and run the library."""
+import numpy as np
+import torch
+
+
+def dev(a, dtype=torch.float64):
+    if a is None:
+        return None
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def run_forces(md, cfg, precision="fp64", pos=None, quat=None, comp=None, model=None, check=False):
+    """Build cells and evaluate forces; returns (numpy dict, Model, Cells)."""
+    pos = cfg["pos"] if pos is None else pos
+    quat = cfg["quat"] if quat is None else quat
+    comp = cfg["comp"] if comp is None else comp
+    m = md.Model(cfg["model"] if model is None else model, check=check)
+    cells = md.Cells()
+    ncomp = len((cfg["model"] if model is None else model)["components"])
+    md.build_cells(m, cells, dev(pos), dev(quat), dev(comp, torch.int32) if ncomp > 1 else None, cfg["box"])
+    r = md.forces(m, cells, precision)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in r.items()}
+    out["U"] = float(out["uw"][0])
+    out["W"] = float(out["uw"][1])
+    out["Wd"] = out["uw"][2:5]
+    out["npairs"] = int(out["npairs"][0])
+    return out, m, cells
+
+
+def rel_rms(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
