@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle rows timed (0: auto)")
     ap.add_argument("--quick", action="store_true", help="short run for profilers: few steps, no extras")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="also run 3 plain device copies of this many MiB (HBM byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
@@ -84,6 +86,14 @@ def main():
     model = md.Model(cfg["model"])
     cells = md.Cells()
     print(f"[bench] workload {args.workload}: N={N}, box={cfg['box'].tolist()}, generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    if args.copy_calib:
+        a = torch.ones(args.copy_calib * 262144, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     # ---- one reference evaluation of the start configuration (both precisions) ----
     pos0 = dev(cfg["pos"])
@@ -200,7 +210,7 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import oracle as O
         rng = np.random.default_rng(7)
-        ns = args.cpu_sample or max(64, int(2.0e9 / N))
+        ns = args.cpu_sample or max(64, int(2.0e10 / N))
         idx = np.sort(rng.choice(N, size=min(ns, N), replace=False))
         t = time.perf_counter()
         ref = O.rows(cfg["model"], cfg["pos"], cfg["quat"], cfg["comp"], cfg["box"], idx)

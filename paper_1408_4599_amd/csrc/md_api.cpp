@@ -283,7 +283,7 @@ int md_cells_destroy(md_cells *c) {
   if (!c) return MD_OK;
   dfree(c->cell_of), dfree(c->slot), dfree(c->tmp), dfree(c->perm), dfree(c->scomp);
   dfree(c->count), dfree(c->start), dfree(c->bsum);
-  dfree(c->sx), dfree(c->sy), dfree(c->sz), dfree(c->svec);
+  dfree(c->sx), dfree(c->sy), dfree(c->sz), dfree(c->svec), dfree(c->xw);
   delete c;
   return MD_OK;
 }
@@ -325,7 +325,8 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
     if ((rc = grow(c->cell_of, cap, N, "cell_of")) || (cap = 0, rc = grow(c->slot, cap, N, "slot")) ||
         (cap = 0, rc = grow(c->tmp, cap, N, "tmp")) || (cap = 0, rc = grow(c->perm, cap, N, "perm")) ||
         (cap = 0, rc = grow(c->scomp, cap, N, "scomp")) || (cap = 0, rc = grow(c->sx, cap, N, "sx")) ||
-        (cap = 0, rc = grow(c->sy, cap, N, "sy")) || (cap = 0, rc = grow(c->sz, cap, N, "sz"))) {
+        (cap = 0, rc = grow(c->sy, cap, N, "sy")) || (cap = 0, rc = grow(c->sz, cap, N, "sz")) ||
+        (cap = 0, rc = grow(c->xw, cap, N, "xw"))) {
       c->cap_N = 0;
       return rc;
     }

@@ -23,6 +23,7 @@ struct BinArgs {
   double Lx, Ly, Lz, ihx, ihy, ihz;
   int32_t nx, ny, nz, ncomp, check_quat;
   int32_t *cell_of, *slot, *count, *status;
+  double *xw;
 };
 
 // Wrap + bin + per-cell histogram.  The returned atomic slot is only a provisional position;
@@ -46,7 +47,9 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
     if (!(fabs(n2 - 1.0) <= 1e-6)) flags |= MD_DEV_QUAT;
   }
   if (flags) atomicOr(a.status, flags);
-  const int cx = bin1(wrap1(x, a.Lx), a.ihx, a.nx);
+  const double xwr = wrap1(x, a.Lx);
+  a.xw[i] = xwr;
+  const int cx = bin1(xwr, a.ihx, a.nx);
   const int cy = bin1(wrap1(y, a.Ly), a.ihy, a.ny);
   const int cz = bin1(wrap1(z, a.Lz), a.ihz, a.nz);
   const int cell = (cz * a.ny + cy) * a.nx + cx;
@@ -138,7 +141,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t *cell_of, const i
 }
 
 struct GatherArgs {
-  const double *pos, *quat;
+  const double *pos, *quat, *xw;
   const int32_t *comp, *cell_of, *start, *tmp;
   int64_t N;
   double Lx, Ly, Lz;
@@ -155,15 +158,22 @@ __device__ __forceinline__ void rotate(const double q[4], const double v[3], dou
   o[2] = 2.0 * (x * z - w * y) * v[0] + 2.0 * (y * z + w * x) * v[1] + (w * w - x * x - y * y + z * z) * v[2];
 }
 
-// Final position of molecule i inside its cell = number of molecules of the same cell with a
-// smaller original index (a stable counting sort); then gather the sorted copies.
+// Final position of molecule i inside its cell = number of molecules of the same cell that come
+// before it in (wrapped x, original index) order; then gather the sorted copies.  Ordering a
+// cell by x makes every x-row of cells x-sorted, which the pair kernel uses to cut its partner
+// windows; ties in x fall back to the original index, so the order is deterministic.
 __global__ __launch_bounds__(256) void k_rank_gather(GatherArgs a) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.N) return;
   const int c = a.cell_of[i];
   const int s = a.start[c], n = a.start[c + 1] - s;
+  const double xi = a.xw[i];
   int rank = 0;
-  for (int k = 0; k < n; ++k) rank += (a.tmp[s + k] < (int32_t)i) ? 1 : 0;
+  for (int k = 0; k < n; ++k) {
+    const int32_t j = a.tmp[s + k];
+    const double xj = a.xw[j];
+    rank += (xj < xi || (xj == xi && j < (int32_t)i)) ? 1 : 0;
+  }
   const int d = s + rank;
   a.perm[d] = (int32_t)i;
   double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
@@ -254,8 +264,10 @@ int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat
                  const double inv_h[3], hipStream_t s) {
   int rc;
   if ((rc = launch_fill_i32(c->count, c->ncell, 0, s))) return rc;
-  BinArgs b{pos, quat, comp, N, c->box[0], c->box[1], c->box[2], inv_h[0], inv_h[1], inv_h[2], c->nc[0], c->nc[1],
-            c->nc[2], m->host.ncomp, (int32_t)((m->flags & MD_CHECK) != 0), c->cell_of, c->slot, c->count, m->status};
+  BinArgs b{pos,      quat,      comp,      N,        c->box[0],       c->box[1],
+            c->box[2], inv_h[0], inv_h[1], inv_h[2], c->nc[0],        c->nc[1],
+            c->nc[2], m->host.ncomp, (int32_t)((m->flags & MD_CHECK) != 0), c->cell_of, c->slot, c->count,
+            m->status, c->xw};
   k_bin<<<nblk(N, 256), 256, 0, s>>>(b);
   if ((rc = check_hip(hipGetLastError(), "k_bin"))) return rc;
   const int64_t nb = (c->ncell + SCAN_TILE - 1) / SCAN_TILE;
@@ -265,7 +277,7 @@ int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat
   if ((rc = check_hip(hipGetLastError(), "k_scan"))) return rc;
   k_scatter<<<nblk(N, 256), 256, 0, s>>>(c->cell_of, c->slot, c->start, N, c->tmp);
   if ((rc = check_hip(hipGetLastError(), "k_scatter"))) return rc;
-  GatherArgs g{pos, m->single_site ? nullptr : quat, comp, c->cell_of, c->start, c->tmp, N, c->box[0], c->box[1],
+  GatherArgs g{pos, m->single_site ? nullptr : quat, c->xw, comp, c->cell_of, c->start, c->tmp, N, c->box[0], c->box[1],
                c->box[2], m->dev, m->shape.lj, m->shape.chg, m->shape.dip, m->shape.quad, c->nvec, c->perm,
                m->single_site ? nullptr : c->scomp, c->sx, c->sy, c->sz, m->single_site ? nullptr : c->svec};
   k_rank_gather<<<nblk(N, 256), 256, 0, s>>>(g);

@@ -57,8 +57,9 @@ struct CellsDev {
   const double *sx, *sy, *sz;  // wrapped COMs in sorted order
   const double *svec;          // [N][nvec][3] world-frame site offsets / axes, sorted order
   int32_t nx, ny, nz, ncell, nvec;
-  double Lx, Ly, Lz;
+  double Lx, Ly, Lz, hx, hy, hz;
 };
+
 
 struct PairOut {
   double *force, *torque, *u_mol, *w_mol;
@@ -86,7 +87,7 @@ struct md_cells {
   const md_model *model = nullptr;
   int32_t *cell_of = nullptr, *slot = nullptr, *tmp = nullptr, *perm = nullptr, *scomp = nullptr;
   int32_t *count = nullptr, *start = nullptr, *bsum = nullptr;
-  double *sx = nullptr, *sy = nullptr, *sz = nullptr, *svec = nullptr;
+  double *sx = nullptr, *sy = nullptr, *sz = nullptr, *svec = nullptr, *xw = nullptr;
 };
 
 struct md_model {

@@ -163,87 +163,298 @@ __device__ __forceinline__ void write_partial(double *partial, double u, double 
 // =====================================================================================
 // Single-site Lennard-Jones (LJ or LJTS, Sec. 2): the molecule is its one site.
 // =====================================================================================
-template <typename R, int CAP>
-__global__ __launch_bounds__(64) void k_pair_lj1(CellsDev c, LJPair p, double rc2, PairOut o) {
-  __shared__ double jx[CAP], jy[CAP], jz[CAP];
-  __shared__ NbTable nb;
-  const int lane = threadIdx.x;
-  const int cell = xcd_remap(blockIdx.x, gridDim.x);
-  double bu = 0.0, bwx = 0.0, bwy = 0.0, bwz = 0.0, bn = 0.0;
-  const int hs = cell < c.ncell ? c.cell_start[cell] : 0;
-  const int hn = cell < c.ncell ? c.cell_start[cell + 1] - hs : 0;
-  if (hn > 0) {
-    build_nb(c, cell, nb);
-    __syncthreads();
-    const int M = nb.off[27];
-    const int self0 = nb.off[13];
-    const int NI = hn <= 16 ? 16 : (hn <= 32 ? 32 : 64);
-    const int NS = 64 / NI;
-    const int il = lane & (NI - 1), sl = lane / NI;
-    const R eps24 = (R)p.eps24, sig2 = (R)p.sig2;
-    const double eps4d = p.eps4, sig2d = p.sig2;
-    for (int ic = 0; ic < hn; ic += 64) {
-      const int iloc = ic + il;
-      const bool act = iloc < hn;
-      double xi = 0.0, yi = 0.0, zi = 0.0;
-      if (act) xi = c.sx[hs + iloc], yi = c.sy[hs + iloc], zi = c.sz[hs + iloc];
-      double fx = 0.0, fy = 0.0, fz = 0.0, uu = 0.0, wx = 0.0, wy = 0.0, wz = 0.0;
-      int nn = 0;
-      for (int jc = 0; jc < M; jc += CAP) {
-        const int mj = min(CAP, M - jc);
-        __syncthreads();
-        for (int t = lane; t < mj; t += 64) {
-          const int g = jc + t;
-          const int k = find_nb(nb.off, g);
-          const int src = nb.start[k] + (g - nb.off[k]);
-          jx[t] = c.sx[src] + nb.sh[k][0];
-          jy[t] = c.sy[src] + nb.sh[k][1];
-          jz[t] = c.sz[src] + nb.sh[k][2];
-        }
-        __syncthreads();
-        if (act) {
-          const int self = self0 + iloc - jc;
-          for (int t = sl; t < mj; t += NS) {
-            const double dx = xi - jx[t], dy = yi - jy[t], dz = zi - jz[t];
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            if (r2 < rc2 && t != self) {
-              // force scalar in R; products with the exact FP64 separation and all sums in FP64
-              const double fs = lj_force_scalar<R>(r2, eps24, sig2);
-              const double gx = fs * dx, gy = fs * dy, gz = fs * dz;
-              fx += gx, fy += gy, fz += gz;
-              wx = fma(gx, dx, wx), wy = fma(gy, dy, wy), wz = fma(gz, dz, wz);
-              // pair energy in FP64 from the reciprocal refined to FP64 accuracy
-              const double ir2 = rcp_fp64_from<R>(r2);
-              const double s2 = sig2d * ir2;
-              const double s6 = s2 * s2 * s2;
-              uu = fma(eps4d * s6, s6 - 1.0, uu);  // LJTS shift: once per pair count, below
-              nn += 1;
-            }
-          }
+
+// One LJ pair seen from molecule i: FP64 separation d (exact), r2 its squared length.
+template <typename R> struct LJAcc {
+  double fx = 0, fy = 0, fz = 0, u = 0, wx = 0, wy = 0, wz = 0;
+  int n = 0;
+  __device__ __forceinline__ void add(double dx, double dy, double dz, double r2, R eps24, R sig2, double eps4d,
+                                      double sig2d) {
+    // force scalar in R; products with the exact FP64 separation and all sums in FP64
+    const double fs = lj_force_scalar<R>(r2, eps24, sig2);
+    const double gx = fs * dx, gy = fs * dy, gz = fs * dz;
+    fx += gx, fy += gy, fz += gz;
+    wx = fma(gx, dx, wx), wy = fma(gy, dy, wy), wz = fma(gz, dz, wz);
+    // pair energy in FP64 from the reciprocal refined to FP64 accuracy (LJTS shift added per count)
+    const double ir2 = rcp_fp64_from<R>(r2);
+    const double s2 = sig2d * ir2;
+    const double s6 = s2 * s2 * s2;
+    u = fma(eps4d * s6, s6 - 1.0, u);
+    n += 1;
+  }
+};
+
+// Fallback for a home cell whose neighbourhood does not fit the LDS tile (or holds more than 64
+// molecules): lanes of wave 0 are split into NI molecule lanes x NS partner slices over the 27
+// cells, staged through LDS in chunks of CAP, every staged partner tested.  Every thread of the
+// block must call it (it synchronises the block).
+template <typename R>
+__device__ void lj1_cell_chunked(const CellsDev &c, const LJPair &p, double rc2, const PairOut &o, int cell,
+                                 double *jx, double *jy, double *jz, const int CAP, NbTable &nb, double acc5[5]) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const bool w0 = tid < 64;
+  const int hs = c.cell_start[cell], hn = c.cell_start[cell + 1] - hs;
+  if (hn == 0) return;
+  __syncthreads();
+  if (w0) build_nb(c, cell, nb);
+  __syncthreads();
+  const int M = nb.off[27];
+  const int self0 = nb.off[13];
+  const int NI = hn <= 16 ? 16 : (hn <= 32 ? 32 : 64);
+  const int NS = 64 / NI;
+  const int il = lane & (NI - 1), sl = lane / NI;
+  const R eps24 = (R)p.eps24, sig2 = (R)p.sig2;
+  for (int ic = 0; ic < hn; ic += 64) {
+    const int iloc = ic + il;
+    const bool act = w0 && iloc < hn;
+    double xi = 0.0, yi = 0.0, zi = 0.0;
+    if (act) xi = c.sx[hs + iloc], yi = c.sy[hs + iloc], zi = c.sz[hs + iloc];
+    LJAcc<R> a;
+    for (int jc = 0; jc < M; jc += CAP) {
+      const int mj = min(CAP, M - jc);
+      __syncthreads();
+      for (int t = tid; t < mj; t += blockDim.x) {
+        const int g = jc + t;
+        const int k = find_nb(nb.off, g);
+        const int src = nb.start[k] + (g - nb.off[k]);
+        jx[t] = c.sx[src] + nb.sh[k][0];
+        jy[t] = c.sy[src] + nb.sh[k][1];
+        jz[t] = c.sz[src] + nb.sh[k][2];
+      }
+      __syncthreads();
+      if (act) {
+        const int self = self0 + iloc - jc;
+        for (int t = sl; t < mj; t += NS) {
+          const double dx = xi - jx[t], dy = yi - jy[t], dz = zi - jz[t];
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          if (r2 < rc2 && t != self) a.add(dx, dy, dz, r2, eps24, sig2, p.eps4, p.sig2);
         }
       }
+    }
+    if (w0) {
 #pragma unroll
       for (int off = 16; off < 64; off <<= 1) {
         if (off >= NI) {
-          fx += __shfl_xor(fx, off), fy += __shfl_xor(fy, off), fz += __shfl_xor(fz, off);
-          uu += __shfl_xor(uu, off);
-          wx += __shfl_xor(wx, off), wy += __shfl_xor(wy, off), wz += __shfl_xor(wz, off);
-          nn += __shfl_xor(nn, off);
+          a.fx += __shfl_xor(a.fx, off), a.fy += __shfl_xor(a.fy, off), a.fz += __shfl_xor(a.fz, off);
+          a.u += __shfl_xor(a.u, off);
+          a.wx += __shfl_xor(a.wx, off), a.wy += __shfl_xor(a.wy, off), a.wz += __shfl_xor(a.wz, off);
+          a.n += __shfl_xor(a.n, off);
         }
       }
-      if (sl == 0 && act) {
-        const int orig = c.perm[hs + iloc];
-        uu -= (double)nn * p.shift;
-        o.force[3 * orig] = fx, o.force[3 * orig + 1] = fy, o.force[3 * orig + 2] = fz;
-        if (o.torque) o.torque[3 * orig] = 0.0, o.torque[3 * orig + 1] = 0.0, o.torque[3 * orig + 2] = 0.0;
-        if (o.u_mol) o.u_mol[orig] = 0.5 * uu;
-        if (o.w_mol) o.w_mol[orig] = 0.5 * (wx + wy + wz);
-        if (o.nnb_mol) o.nnb_mol[orig] = nn;
-        bu += 0.5 * uu, bwx += 0.5 * wx, bwy += 0.5 * wy, bwz += 0.5 * wz, bn += (double)nn;
+    }
+    if (act && sl == 0) {
+      const int orig = c.perm[hs + iloc];
+      a.u -= (double)a.n * p.shift;
+      o.force[3 * orig] = a.fx, o.force[3 * orig + 1] = a.fy, o.force[3 * orig + 2] = a.fz;
+      if (o.torque) o.torque[3 * orig] = 0.0, o.torque[3 * orig + 1] = 0.0, o.torque[3 * orig + 2] = 0.0;
+      if (o.u_mol) o.u_mol[orig] = 0.5 * a.u;
+      if (o.w_mol) o.w_mol[orig] = 0.5 * (a.wx + a.wy + a.wz);
+      if (o.nnb_mol) o.nnb_mol[orig] = a.n;
+      acc5[0] += 0.5 * a.u, acc5[1] += 0.5 * a.wx, acc5[2] += 0.5 * a.wy, acc5[3] += 0.5 * a.wz;
+      acc5[4] += (double)a.n;
+    }
+  }
+}
+
+// Fixed-order block reduction of the five partial columns (wave shuffles, then waves in order).
+template <int NW>
+__device__ __forceinline__ void write_partial_block(double *partial, double acc5[5], double (*red)[5]) {
+#pragma unroll
+  for (int q = 0; q < 5; ++q)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc5[q] += __shfl_xor(acc5[q], o);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (NW == 1) {
+    if (lane == 0) {
+      double *pp = partial + (int64_t)blockIdx.x * PARTIAL_COLS;
+      for (int q = 0; q < 5; ++q) pp[q] = acc5[q];
+    }
+    return;
+  }
+  if (lane == 0)
+    for (int q = 0; q < 5; ++q) red[wave][q] = acc5[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double *pp = partial + (int64_t)blockIdx.x * PARTIAL_COLS;
+    for (int q = 0; q < 5; ++q) {
+      double v = red[0][q];
+      for (int w = 1; w < NW; ++w) v += red[w][q];
+      pp[q] = v;
+    }
+  }
+}
+
+// Quad-cell kernel with compaction.  A block of four wavefronts takes a 2 x 2 group of home
+// cells (x, y) in one z-layer; their 27-cell neighbourhoods together span 4 x 4 x 3 cells, which
+// are staged once into LDS (image shifts applied) in x-fastest order, so each wavefront's stencil
+// is nine contiguous x-rows of three cells.  In a wavefront, lanes = NI molecules x NS partner
+// slices (NI = 16, 32 or 64 from the home-cell occupancy) and lane (i, s) scans row entries
+// s, s + NS, ...: all molecule lanes of a slice read the same partner, so LDS reads broadcast.
+// Pass 1 runs only the exact FP64 cutoff test and appends hits to a per-lane list in LDS (a full
+// list evaluates further hits at once); pass 2 evaluates the interactions of the listed hits, so
+// the pair arithmetic runs for partners inside the cutoff only.  A tile that does not fit falls
+// back to lj1_cell_chunked for each home cell.
+constexpr int QCELLS = 48;  // 4 x 4 x 3 staged cells
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double rc2, PairOut o, int cap, int lcap) {
+  extern __shared__ double dyn[];
+  double *jx = dyn, *jy = dyn + cap, *jz = dyn + 2 * cap;
+  unsigned short *list = (unsigned short *)(dyn + 3 * cap);
+  __shared__ int qoff[QCELLS + 1], qstart[QCELLS];
+  __shared__ double qsh[QCELLS][3];
+  __shared__ NbTable nb;
+  __shared__ double red[4][5];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nbx = (c.nx + 1) >> 1, nby = (c.ny + 1) >> 1;
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (b < nbx * nby * c.nz) {
+    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+    // tile cell u = ux + 4 uy + 16 uz covers cell (2 bx - 1 + ux, 2 by - 1 + uy, bz - 1 + uz)
+    if (tid < 64) {
+      int cnt = 0;
+      if (tid < QCELLS) {
+        int x = 2 * bx - 1 + (tid & 3), y = 2 * by - 1 + ((tid >> 2) & 3), z = bz - 1 + (tid >> 4);
+        double shx = 0.0, shy = 0.0, shz = 0.0;
+        if (x < 0) x += c.nx, shx = -c.Lx;
+        else if (x >= c.nx) x -= c.nx, shx = c.Lx;
+        if (y < 0) y += c.ny, shy = -c.Ly;
+        else if (y >= c.ny) y -= c.ny, shy = c.Ly;
+        if (z < 0) z += c.nz, shz = -c.Lz;
+        else if (z >= c.nz) z -= c.nz, shz = c.Lz;
+        const int cc = (z * c.ny + y) * c.nx + x;
+        const int s0 = c.cell_start[cc];
+        cnt = c.cell_start[cc + 1] - s0;
+        qstart[tid] = s0;
+        qsh[tid][0] = shx, qsh[tid][1] = shy, qsh[tid][2] = shz;
+      }
+      const int incl = wave_incl_scan(cnt);
+      if (tid < QCELLS) qoff[tid] = incl - cnt;
+      if (tid == QCELLS - 1) qoff[QCELLS] = incl;
+    }
+    __syncthreads();
+    const int U = qoff[QCELLS];
+    // this wavefront's home cell
+    const int hx = wave & 1, hy = wave >> 1;
+    const int cx = 2 * bx + hx, cy = 2 * by + hy;
+    const bool hvalid = cx < c.nx && cy < c.ny;
+    const int hcell = hvalid ? (bz * c.ny + cy) * c.nx + cx : 0;
+    const int hs = hvalid ? c.cell_start[hcell] : 0;
+    const int hn = hvalid ? c.cell_start[hcell + 1] - hs : 0;
+    const int bad = (U > cap) || (hn > 64);
+    if (!__syncthreads_or(bad)) {
+      for (int t = tid; t < U; t += 256) {
+        int lo = 0, hi = QCELLS;  // last tile cell with qoff <= t
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (qoff[mid] <= t) lo = mid;
+          else hi = mid;
+        }
+        const int src = qstart[lo] + (t - qoff[lo]);
+        jx[t] = c.sx[src] + qsh[lo][0];
+        jy[t] = c.sy[src] + qsh[lo][1];
+        jz[t] = c.sz[src] + qsh[lo][2];
+      }
+      __syncthreads();
+      if (hn > 0) {
+        const int NI = hn <= 16 ? 16 : (hn <= 32 ? 32 : 64);
+        const int NS = 64 / NI;
+        const int il = lane & (NI - 1), sl = lane / NI;
+        const bool act = il < hn;
+        const int self = qoff[(hx + 1) + 4 * (hy + 1) + 16] + il;
+        unsigned short *mylist = list + (size_t)wave * 64 * lcap + lane;
+        LJAcc<R> a;
+        const R eps24 = (R)p.eps24, sig2 = (R)p.sig2;
+        if (act) {
+          const double xi = jx[self], yi = jy[self], zi = jz[self];
+          int cnt = 0;
+          for (int r = 0; r < 9; ++r) {
+            const int u0 = hx + 4 * (hy + r % 3) + 16 * (r / 3);
+            const int lo = qoff[u0], hi = qoff[u0 + 3];
+            int t = lo + sl;
+            for (; t + NS < hi; t += 2 * NS) {
+              const int t2 = t + NS;
+              const double ax = xi - jx[t], ay = yi - jy[t], az = zi - jz[t];
+              const double bx_ = xi - jx[t2], by_ = yi - jy[t2], bz_ = zi - jz[t2];
+              const double ra = fma(az, az, fma(ay, ay, ax * ax));
+              const double rb = fma(bz_, bz_, fma(by_, by_, bx_ * bx_));
+              if (ra < rc2 && t != self) {
+                if (cnt < lcap) mylist[64 * cnt++] = (unsigned short)t;
+                else a.add(ax, ay, az, ra, eps24, sig2, p.eps4, p.sig2);
+              }
+              if (rb < rc2 && t2 != self) {
+                if (cnt < lcap) mylist[64 * cnt++] = (unsigned short)t2;
+                else a.add(bx_, by_, bz_, rb, eps24, sig2, p.eps4, p.sig2);
+              }
+            }
+            if (t < hi) {
+              const double ax = xi - jx[t], ay = yi - jy[t], az = zi - jz[t];
+              const double ra = fma(az, az, fma(ay, ay, ax * ax));
+              if (ra < rc2 && t != self) {
+                if (cnt < lcap) mylist[64 * cnt++] = (unsigned short)t;
+                else a.add(ax, ay, az, ra, eps24, sig2, p.eps4, p.sig2);
+              }
+            }
+          }
+          for (int k = 0; k < cnt; ++k) {
+            const int u = mylist[64 * k];
+            const double dx = xi - jx[u], dy = yi - jy[u], dz = zi - jz[u];
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            a.add(dx, dy, dz, r2, eps24, sig2, p.eps4, p.sig2);
+          }
+        }
+#pragma unroll
+        for (int off = 16; off < 64; off <<= 1) {
+          if (off >= NI) {
+            a.fx += __shfl_xor(a.fx, off), a.fy += __shfl_xor(a.fy, off), a.fz += __shfl_xor(a.fz, off);
+            a.u += __shfl_xor(a.u, off);
+            a.wx += __shfl_xor(a.wx, off), a.wy += __shfl_xor(a.wy, off), a.wz += __shfl_xor(a.wz, off);
+            a.n += __shfl_xor(a.n, off);
+          }
+        }
+        if (act && sl == 0) {
+          const int orig = c.perm[hs + il];
+          a.u -= (double)a.n * p.shift;
+          o.force[3 * orig] = a.fx, o.force[3 * orig + 1] = a.fy, o.force[3 * orig + 2] = a.fz;
+          if (o.torque) o.torque[3 * orig] = 0.0, o.torque[3 * orig + 1] = 0.0, o.torque[3 * orig + 2] = 0.0;
+          if (o.u_mol) o.u_mol[orig] = 0.5 * a.u;
+          if (o.w_mol) o.w_mol[orig] = 0.5 * (a.wx + a.wy + a.wz);
+          if (o.nnb_mol) o.nnb_mol[orig] = a.n;
+          acc5[0] = 0.5 * a.u, acc5[1] = 0.5 * a.wx, acc5[2] = 0.5 * a.wy, acc5[3] = 0.5 * a.wz;
+          acc5[4] = (double)a.n;
+        }
+      }
+    } else {
+      for (int w = 0; w < 4; ++w) {
+        const int fx = 2 * bx + (w & 1), fy = 2 * by + (w >> 1);
+        if (fx < c.nx && fy < c.ny)
+          lj1_cell_chunked<R>(c, p, rc2, o, (bz * c.ny + fy) * c.nx + fx, jx, jy, jz, cap, nb, acc5);
       }
     }
   }
-  write_partial(o.partial, bu, bwx, bwy, bwz, bn);
+  write_partial_block<4>(o.partial, acc5, red);
+}
+
+// Staged-partner capacity of the LJ tile: the 48 tile cells at 1.3 x the mean occupancy (+ one
+// wave), rounded to 64; denser neighbourhoods take the chunked fallback.  (Per-lane list entries
+// are 16-bit staged indices, so the cap stays below 65536.)
+inline int lj1_tile_cap(int64_t N, int64_t ncell) {
+  const double mean = (double)N / (double)ncell;
+  int cap = (int)(QCELLS * mean * 1.3) + 64;
+  cap = (cap + 63) / 64 * 64;
+  return cap < 256 ? 256 : (cap > 4096 ? 4096 : cap);
+}
+
+// Per-lane hit-list length: expected partners per molecule (4/3 pi r_c^3 N/V) over the slices of
+// a lane, with margin; hits beyond it are evaluated inline.
+inline int lj1_list_cap(int64_t N, double V, double rc, int64_t ncell) {
+  const double mean = (double)N / (double)ncell;
+  const int NS = mean <= 16.0 ? 4 : (mean <= 32.0 ? 2 : 1);
+  const double hits = 4.18879020478639 * rc * rc * rc * (double)N / V / NS;
+  int l = (int)(1.4 * hits) + 8;
+  l = (l + 7) / 8 * 8;
+  return l < 16 ? 16 : (l > 96 ? 96 : l);
 }
 
 // =====================================================================================
@@ -604,6 +815,7 @@ CellsDev cells_dev(const md_cells *c) {
   d.ncell = (int32_t)c->ncell;
   d.nvec = c->nvec;
   d.Lx = c->box[0], d.Ly = c->box[1], d.Lz = c->box[2];
+  d.hx = c->box[0] / c->nc[0], d.hy = c->box[1] / c->nc[1], d.hz = c->box[2] / c->nc[2];
   return d;
 }
 
@@ -614,8 +826,13 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
   const bool f32 = precision == MD_FP32;
   if (m->single_site) {
     const LJPair p = m->host.lj[0][0][0][0];
-    if (f32) k_pair_lj1<float, 512><<<(unsigned)nb, 64, 0, s>>>(cd, p, m->host.rc2, o);
-    else k_pair_lj1<double, 512><<<(unsigned)nb, 64, 0, s>>>(cd, p, m->host.rc2, o);
+    const int cap = lj1_tile_cap(c->N, c->ncell);
+    const int lcap = lj1_list_cap(c->N, c->box[0] * c->box[1] * c->box[2], m->host.rc, c->ncell);
+    const size_t lds = (size_t)cap * 3 * sizeof(double) + (size_t)lcap * 256 * sizeof(unsigned short);
+    const int64_t nq = pair_blocks((int64_t)((c->nc[0] + 1) / 2) * ((c->nc[1] + 1) / 2) * c->nc[2]);
+    *nblocks = nq;
+    if (f32) k_pair_lj1<float><<<(unsigned)nq, 256, lds, s>>>(cd, p, m->host.rc2, o, cap, lcap);
+    else k_pair_lj1<double><<<(unsigned)nq, 256, lds, s>>>(cd, p, m->host.rc2, o, cap, lcap);
     return check_hip(hipGetLastError(), "k_pair_lj1");
   }
   const Shape &S = m->shape;

@@ -51,7 +51,7 @@ CELL_CASES = {
 def test_cells_bit_exact(md, oracle, case):
     cfg = CELL_CASES[case]()
     pos = cfg["pos"] * (3.0 if case == "outside_box" else 1.0) - (7.0 if case == "outside_box" else 0.0)
-    ref_cell, _, ncell = oracle.bin_cells(pos, cfg["box"], cfg["model"]["rc"])
+    ref_cell, ref_w, ncell = oracle.bin_cells(pos, cfg["box"], cfg["model"]["rc"])
     _, m, cells = run_forces(md, cfg, "fp64", pos=pos)
     v = cells.view()
     assert v["ncell"] == ncell and v["nc"] == oracle.ncells(cfg["box"], cfg["model"]["rc"])
@@ -61,7 +61,9 @@ def test_cells_bit_exact(md, oracle, case):
     start = v["cell_start"].cpu().numpy()
     np.testing.assert_array_equal(np.diff(start), counts)
     assert start[0] == 0 and start[-1] == len(ref_cell)
-    np.testing.assert_array_equal(v["perm"].cpu().numpy(), np.argsort(ref_cell, kind="stable"))
+    # sorted by cell, inside a cell by wrapped x, ties by original index
+    order = np.lexsort((np.arange(len(ref_cell)), ref_w[:, 0], ref_cell))
+    np.testing.assert_array_equal(v["perm"].cpu().numpy(), order)
 
 
 FORCE_CASES = ["c1_ljts_4000", "c4_small", "c5_small", "mixture_small", "gas_ragged", "one_cell"]
