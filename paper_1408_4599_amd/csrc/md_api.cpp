@@ -213,12 +213,16 @@ int md_model_create(const md_component_desc *comps, int32_t ncomp, const double 
           p.eps4 = 4.0 * eps;
           p.eps24 = 24.0 * eps;
           p.sig2 = sig * sig;
+          p.pe = 0.5 / h.comp[A].lj_eps[a];
+          p.ps = 0.5 * h.eta[A][B] * 4.0 * eps / sig;
           if (h.lj_shift) {
             const double c2 = sig * sig / h.rc2;
             const double c6 = c2 * c2 * c2;
             p.shift = 4.0 * eps * (c6 * c6 - c6);
+            p.csh = 12.0 * c6 * c6 - 6.0 * c6;
           } else {
             p.shift = 0.0;
+            p.csh = 0.0;
           }
           h.shift_sum[A][B] += p.shift;
         }
@@ -239,6 +243,8 @@ int md_model_create(const md_component_desc *comps, int32_t ncomp, const double 
     off += 5 * comps[c].n_lj + 4 * (comps[c].n_chg + comps[c].n_dip + comps[c].n_quad);
   }
   tmp.nparam = off;
+  for (int c = 0; c < ncomp; ++c) h.param_off[c] = (int32_t)tmp.param_off[c];
+  h.nparam = (int32_t)off;
   tmp.flags = flags;
 
   md_model *m = new md_model(tmp);
@@ -355,6 +361,7 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
   for (int k = 0; k < 3; ++k) c->nc[k] = nc[k], c->box[k] = box[k];
   c->nvec = nvec;
   c->model = m;
+  c->quat = quat;
   c->built = false;
   const double inv_h[3] = {(double)nc[0] / box[0], (double)nc[1] / box[1], (double)nc[2] / box[2]};
   hipEvent_t ev;
@@ -447,7 +454,7 @@ int md_forces_adjoint(md_model *m, const md_cells *c, int precision, double gU, 
   int64_t nblocks = 0;
   hipEvent_t ev;
   prof_begin(m, PROF_ADJ, s, &ev);
-  rc = launch_adjoint(m, c, precision, o, s, &nblocks);
+  rc = launch_adjoint(m, c, precision, o, m->single_site ? nullptr : c->quat, s, &nblocks);
   if (!rc && pg) rc = launch_reduce(m, nblocks, (int)m->nparam, pg, dparams, s);
   prof_end(m, PROF_ADJ, s, ev);
   if (rc) return rc;

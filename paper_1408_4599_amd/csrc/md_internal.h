@@ -34,9 +34,12 @@ struct CompDev {
   double mass, inv_mass, inertia[3], inv_inertia[3];
 };
 
-// LJ parameters of one site pair (a of component A, b of component B) after mixing.
+// LJ parameters of one site pair (a of component A, b of component B) after mixing, plus the
+// adjoint's factors: pe = 1 / (2 eps_a) (d eps_ab / d eps_a = eps_ab pe, and u is linear in
+// eps_ab), ps = (eta_AB / 2) 4 eps_ab / sigma_ab, csh = 12 (sigma_ab/r_c)^12 - 6 (sigma_ab/r_c)^6
+// when shifted (else 0): du/dsigma_a = ps (12 s^12 - 6 s^6 - csh).
 struct LJPair {
-  double eps4, eps24, sig2, shift;
+  double eps4, eps24, sig2, shift, pe, ps, csh, pad_;
 };
 
 struct ModelDev {
@@ -49,6 +52,8 @@ struct ModelDev {
   // sum of the LJTS shifts u_ab(r_c) over all LJ site pairs of a component pair: subtracted once
   // per interacting molecule pair in FP64 (a per-pair rounded constant would bias U)
   double shift_sum[MD_MAX_COMP][MD_MAX_COMP];
+  int32_t param_off[MD_MAX_COMP];  // first parameter-gradient column of each component
+  int32_t nparam;
 };
 
 // Everything a pair kernel needs about the sorted configuration.
@@ -85,6 +90,7 @@ struct md_cells {
   int nvec = 0, cap_nvec = 0;
   bool built = false;
   const md_model *model = nullptr;
+  const double *quat = nullptr;  // caller's quaternion array of the last build (read by the adjoint)
   int32_t *cell_of = nullptr, *slot = nullptr, *tmp = nullptr, *perm = nullptr, *scomp = nullptr;
   int32_t *count = nullptr, *start = nullptr, *bsum = nullptr;
   double *sx = nullptr, *sy = nullptr, *sz = nullptr, *svec = nullptr, *xw = nullptr;
@@ -140,7 +146,8 @@ int launch_finish_forces(const double *sums, double *uw, int64_t *npairs, double
 int launch_leapfrog(md_model *m, double *pos, double *vel, double *quat, double *angmom, const int32_t *comp,
                     int64_t N, const double box[3], double dt, const double *force, const double *torque,
                     double *energies_row, hipStream_t s);
-int launch_adjoint(md_model *m, const md_cells *c, int precision, const AdjOut &o, hipStream_t s, int64_t *nblocks);
+int launch_adjoint(md_model *m, const md_cells *c, int precision, const AdjOut &o, const double *quat,
+                   hipStream_t s, int64_t *nblocks);
 int launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 int launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 int launch_scale_copy(const double *src, double *dst, int64_t n, double a, hipStream_t s);

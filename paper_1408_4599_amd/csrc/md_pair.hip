@@ -17,132 +17,10 @@
 // Every pair is evaluated from both ends (full shell), so no atomics are needed and results are
 // bitwise reproducible.  The pair work is VALU-bound (no dense contraction: no MFMA).
 
-#include "md_internal.h"
+#include "md_device.h"
 
 namespace mdcell {
 namespace {
-
-// ---------------------------------------------------------------- arithmetic helpers
-// Reciprocal and reciprocal square root: the hardware estimate refined by Newton-Raphson
-// iterations (r <- r + r (1 - x r); y <- y + y (1 - x y^2) / 2), once in FP32, twice / three
-// times in FP64.
-template <typename R> __device__ __forceinline__ R rcp_nr(R x);
-template <> __device__ __forceinline__ float rcp_nr<float>(float x) {
-  const float r = __builtin_amdgcn_rcpf(x);
-  const float e = fmaf(-x, r, 1.0f);
-  return fmaf(r, e, r);
-}
-template <> __device__ __forceinline__ double rcp_nr<double>(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-template <typename R> __device__ __forceinline__ R rsq_nr(R x);
-template <> __device__ __forceinline__ float rsq_nr<float>(float x) {
-  const float y = __builtin_amdgcn_rsqf(x);
-  const float h = x * y;
-  const float e = fmaf(-h, y, 1.0f);
-  return fmaf(0.5f * y, e, y);
-}
-template <> __device__ __forceinline__ double rsq_nr<double>(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double h = x * y;
-    const double e = fma(-h, y, 1.0);
-    y = fma(0.5 * y, e, y);
-  }
-  return y;
-}
-
-template <typename R> __device__ __forceinline__ void addto(double &a, R x) { a += (double)x; }
-
-// LJ force scalar fs = 24 eps s^6 (2 s^6 - 1) / r^2 (force on i = fs * r_ij), evaluated in R from
-// the FP64 squared distance.  FP32: one hardware reciprocal (1 ulp), no refinement -- the force
-// error budget is 1e-5 relative.  FP64: reciprocal refined by two Newton steps.
-template <typename R> __device__ __forceinline__ double lj_force_scalar(double r2, R eps24, R sig2);
-template <> __device__ __forceinline__ double lj_force_scalar<float>(double r2, float eps24, float sig2) {
-  const float ir2 = __builtin_amdgcn_rcpf((float)r2);
-  const float s2 = sig2 * ir2;
-  const float s6 = s2 * s2 * s2;
-  return (double)((eps24 * ir2) * (s6 * fmaf(2.0f, s6, -1.0f)));
-}
-template <> __device__ __forceinline__ double lj_force_scalar<double>(double r2, double eps24, double sig2) {
-  const double ir2 = rcp_nr<double>(r2);
-  const double s2 = sig2 * ir2;
-  const double s6 = s2 * s2 * s2;
-  return (eps24 * ir2) * (s6 * fma(2.0, s6, -1.0));
-}
-// 1 / r2 to FP64 accuracy: FP32 path starts from the FP32 hardware reciprocal (recomputed; the
-// compiler merges it with the one in lj_force_scalar) and takes one FP64 Newton step (2^-23 ->
-// ~2^-46 relative); FP64 path uses the twice-refined FP64 reciprocal.
-template <typename R> __device__ __forceinline__ double rcp_fp64_from(double r2);
-template <> __device__ __forceinline__ double rcp_fp64_from<float>(double r2) {
-  double r = (double)__builtin_amdgcn_rcpf((float)r2);
-  const double e = fma(-r2, r, 1.0);
-  return fma(r, e, r);
-}
-template <> __device__ __forceinline__ double rcp_fp64_from<double>(double r2) { return rcp_nr<double>(r2); }
-
-__device__ __forceinline__ int wave_incl_scan(int v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(v, o, 64);
-    if (lane >= o) v += t;
-  }
-  return v;
-}
-
-// ---------------------------------------------------------------- neighbour-cell table
-struct NbTable {
-  int off[28];   // exclusive prefix of the 27 cell counts (off[27] = total staged)
-  int start[27]; // first sorted slot of each neighbour cell
-  double sh[27][3];
-};
-
-// Stencil entry k = 0..26 is (dx, dy, dz) = (k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1); entry 13
-// is the home cell.  A neighbour index that leaves the grid wraps around, and the molecules of
-// the wrapped cell are seen through the image shift -L (from below) or +L (from above).
-__device__ __forceinline__ void build_nb(const CellsDev &c, int cell, NbTable &t) {
-  const int lane = threadIdx.x;
-  int cnt = 0;
-  if (lane < 27) {
-    const int cx = cell % c.nx, cy = (cell / c.nx) % c.ny, cz = cell / (c.nx * c.ny);
-    int x = cx + lane % 3 - 1, y = cy + (lane / 3) % 3 - 1, z = cz + lane / 9 - 1;
-    double shx = 0.0, shy = 0.0, shz = 0.0;
-    if (x < 0) x += c.nx, shx = -c.Lx;
-    else if (x >= c.nx) x -= c.nx, shx = c.Lx;
-    if (y < 0) y += c.ny, shy = -c.Ly;
-    else if (y >= c.ny) y -= c.ny, shy = c.Ly;
-    if (z < 0) z += c.nz, shz = -c.Lz;
-    else if (z >= c.nz) z -= c.nz, shz = c.Lz;
-    const int nc = (z * c.ny + y) * c.nx + x;
-    const int s = c.cell_start[nc];
-    cnt = c.cell_start[nc + 1] - s;
-    t.start[lane] = s;
-    t.sh[lane][0] = shx;
-    t.sh[lane][1] = shy;
-    t.sh[lane][2] = shz;
-  }
-  const int incl = wave_incl_scan(cnt);
-  if (lane < 27) t.off[lane] = incl - cnt;
-  if (lane == 26) t.off[27] = incl;
-}
-
-// Last stencil entry k with off[k] <= g (skips empty cells).
-__device__ __forceinline__ int find_nb(const int *off, int g) {
-  int lo = 0, hi = 27;
-#pragma unroll
-  for (int it = 0; it < 5; ++it) {
-    const int mid = (lo + hi) >> 1;
-    if (off[mid] <= g) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
 
 // ---------------------------------------------------------------- block partials
 __device__ __forceinline__ void write_partial(double *partial, double u, double wx, double wy, double wz, double n) {
@@ -462,72 +340,6 @@ inline int lj1_list_cap(int64_t N, double V, double rc, int64_t ncell) {
 // dipoles, linear point quadrupoles (k_C = 1) + reaction field on dipole pairs.
 // =====================================================================================
 
-// Energy per unit moment product of one electrostatic site pair and its partial derivatives
-// with respect to r and the cosines c_i = e_a.rhat, c_j = e_b.rhat, c_ij = e_a.e_b (rhat points
-// from site b of molecule j to site a of molecule i).  ir = 1/r; krc3 = kappa / r_c^3.
-template <typename R> struct Unit {
-  R t, tr, ti, tj, tij;
-};
-
-template <int KA, int KB, typename R>
-__device__ __forceinline__ Unit<R> unit_terms(R ir, R ci, R cj, R cij, R krc3) {
-  Unit<R> u{0, 0, 0, 0, 0};
-  const R ir2 = ir * ir, ir3 = ir2 * ir, ir4 = ir3 * ir;
-  if constexpr (KA == KIND_CHG && KB == KIND_CHG) {
-    u.t = ir;
-    u.tr = -ir2;
-  } else if constexpr (KA == KIND_CHG && KB == KIND_DIP) {
-    u.t = cj * ir2;
-    u.tr = (R)-2 * cj * ir3;
-    u.tj = ir2;
-  } else if constexpr (KA == KIND_DIP && KB == KIND_CHG) {
-    u.t = -ci * ir2;
-    u.tr = (R)2 * ci * ir3;
-    u.ti = -ir2;
-  } else if constexpr (KA == KIND_CHG && KB == KIND_QUAD) {
-    u.t = (R)0.5 * fma((R)3 * cj, cj, (R)-1) * ir3;
-    u.tr = (R)-3 * u.t * ir;
-    u.tj = (R)3 * cj * ir3;
-  } else if constexpr (KA == KIND_QUAD && KB == KIND_CHG) {
-    u.t = (R)0.5 * fma((R)3 * ci, ci, (R)-1) * ir3;
-    u.tr = (R)-3 * u.t * ir;
-    u.ti = (R)3 * ci * ir3;
-  } else if constexpr (KA == KIND_DIP && KB == KIND_DIP) {
-    const R g = fma((R)-3 * ci, cj, cij);
-    u.t = fma(g, ir3, -krc3 * cij);
-    u.tr = (R)-3 * g * ir4;
-    u.ti = (R)-3 * cj * ir3;
-    u.tj = (R)-3 * ci * ir3;
-    u.tij = ir3 - krc3;
-  } else if constexpr (KA == KIND_DIP && KB == KIND_QUAD) {
-    const R p = (R)1.5 * ir4;
-    const R g = ci - (R)5 * ci * cj * cj + (R)2 * cj * cij;
-    u.t = p * g;
-    u.tr = (R)-4 * u.t * ir;
-    u.ti = p * fma((R)-5 * cj, cj, (R)1);
-    u.tj = p * fma((R)-10 * ci, cj, (R)2 * cij);
-    u.tij = p * (R)2 * cj;
-  } else if constexpr (KA == KIND_QUAD && KB == KIND_DIP) {
-    const R p = (R)-1.5 * ir4;
-    const R g = cj - (R)5 * cj * ci * ci + (R)2 * ci * cij;
-    u.t = p * g;
-    u.tr = (R)-4 * u.t * ir;
-    u.tj = p * fma((R)-5 * ci, ci, (R)1);
-    u.ti = p * fma((R)-10 * ci, cj, (R)2 * cij);
-    u.tij = p * (R)2 * ci;
-  } else {  // QUAD-QUAD
-    const R p = (R)0.75 * ir4 * ir;
-    const R s = fma((R)-5 * ci, cj, cij);
-    const R ci2 = ci * ci, cj2 = cj * cj;
-    u.t = p * ((R)1 - (R)5 * ci2 - (R)5 * cj2 - (R)15 * ci2 * cj2 + (R)2 * s * s);
-    u.tr = (R)-5 * u.t * ir;
-    u.ti = p * ((R)-10 * ci - (R)30 * ci * cj2 - (R)20 * cj * s);
-    u.tj = p * ((R)-10 * cj - (R)30 * cj * ci2 - (R)20 * ci * s);
-    u.tij = p * (R)4 * s;
-  }
-  return u;
-}
-
 template <typename R> __device__ __forceinline__ void cross_acc(R *T, const R *a, const R *f) {
   T[0] += a[1] * f[2] - a[2] * f[1];
   T[1] += a[2] * f[0] - a[0] * f[2];
@@ -573,14 +385,6 @@ __device__ __forceinline__ void elec_site(R pm, const R *oa, const R *ea, const 
   }
   acc.u += pm * t.t;
 }
-
-// Slot layout of the per-molecule vectors for shape (SL, SC, SD, SQ).
-template <int SL, int SC, int SD, int SQ> struct Slots {
-  static constexpr int lj = 0, chg = SL, dip = SL + SC, dipax = SL + SC + SD, quad = SL + SC + 2 * SD,
-                       quadax = SL + SC + 2 * SD + SQ, nv = SL + SC + 2 * SD + 2 * SQ;
-};
-
-template <int KA, int KB> struct KindSlots;
 
 // All electrostatic site pairs of kinds (KA on i, KB on j).
 template <int KA, int KB, int SL, int SC, int SD, int SQ, bool MIX, typename R>

@@ -1,0 +1,78 @@
+"""GPU md_step (leapfrog translation + quaternion rotation, cell rebuild every step) against the
+FP64 oracle's integrator on the same seeded states.  Trajectories are compared after a short run
+(rounding differences grow chaotically, so the bars are loose absolute position tolerances well
+below any physical scale) and the per-step energies term by term."""
+import numpy as np
+import pytest
+import torch
+
+from tests._gpu import dev
+from paper_1408_4599_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def md():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1408_4599_amd import md as _md
+    _md.lib()
+    return _md
+
+
+def _run_gpu(md, cfg, nsteps, precision="fp64", dt=None):
+    m = md.Model(cfg["model"])
+    cells = md.Cells()
+    pos, vel = dev(cfg["pos"]), dev(cfg["vel"])
+    quat, ang = dev(cfg["quat"]), dev(cfg["angmom"])
+    ncomp = len(cfg["model"]["components"])
+    comp = dev(cfg["comp"], torch.int32) if ncomp > 1 else None
+    en = md.step(m, cells, pos, vel, quat, ang, comp, cfg["box"], dt or cfg["dt"], nsteps, precision)
+    torch.cuda.synchronize()
+    return (pos.cpu().numpy(), vel.cpu().numpy(), None if quat is None else quat.cpu().numpy(),
+            None if ang is None else ang.cpu().numpy(), en.cpu().numpy())
+
+
+def _min_image(d, box):
+    return d - box * np.round(d / box)
+
+
+@pytest.mark.parametrize("name,nsteps,tol", [("c1_ljts_4000", 100, 1e-9), ("c4_small", 20, 1e-9),
+                                             ("mixture_small", 20, 1e-9)])
+def test_step_fp64_matches_oracle_trajectory(md, oracle, name, nsteps, tol):
+    cfg = W.make(name)
+    p_ref, v_ref, q_ref, j_ref, e_ref = oracle.step(cfg["model"], cfg["pos"], cfg["vel"], cfg["quat"], cfg["angmom"],
+                                                    cfg["comp"], cfg["box"], cfg["dt"], nsteps)
+    p, v, q, j, e = _run_gpu(md, cfg, nsteps)
+    assert np.abs(_min_image(p - p_ref, cfg["box"])).max() < tol
+    assert np.abs(v - v_ref).max() < 1e3 * tol
+    if q is not None:
+        assert np.abs(q - q_ref).max() < 1e3 * tol
+        assert np.abs(j - j_ref).max() < 1e3 * tol
+    # U, K_trans, K_rot, W per step
+    np.testing.assert_allclose(e, e_ref, rtol=1e-9, atol=1e-9 * np.abs(e_ref).max())
+
+
+def test_step_nve_fp32_energy_conservation(md):
+    """FP32 path over 200 steps of C1: the total energy stays within the band of the FP64 path."""
+    cfg = W.make("c1_ljts_4000")
+    *_, e32 = _run_gpu(md, cfg, 200, "fp32")
+    *_, e64 = _run_gpu(md, cfg, 200, "fp64")
+    E32, E64 = e32[:, :3].sum(1), e64[:, :3].sum(1)
+    s32 = np.abs(E32 - E32[0]).max() / abs(E32[0])
+    s64 = np.abs(E64 - E64[0]).max() / abs(E64[0])
+    assert s64 < 2e-4
+    assert s32 < 1.5 * s64 + 1e-6
+
+
+def test_step_checkpoint_resume_is_bitwise(md):
+    """100 steps equal 50 steps, copy the state out (checkpoint), then 50 more from the copy."""
+    cfg = W.make("c4_small")
+    a = _run_gpu(md, cfg, 40)
+    half = _run_gpu(md, cfg, 20)
+    cfg2 = dict(cfg, pos=half[0], vel=half[1], quat=half[2], angmom=half[3])
+    b = _run_gpu(md, cfg2, 20)
+    for x, y in zip(a[:4], b[:4]):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(a[4][20:], b[4])
