@@ -48,6 +48,87 @@ def distance_tests(counts3d):
     return float(nd.sum() - 0.5 * c.sum())
 
 
+def pair_traffic(kernel_sources):
+    """HBM bytes per pair-kernel launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source (hash recorded in the summary); else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_pair_lj1_c2_lj_1m_counters.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in kernel_sources:
+        h.update(open(os.path.join(ROOT, "paper_1408_4599_amd", "csrc", f), "rb").read())
+    text = open(path).read()
+    src, val = None, None
+    for line in text.splitlines():
+        if line.startswith("source_sha256:"):
+            src = line.split(":", 1)[1].strip()
+        if line.startswith("traffic_bytes_per_launch:"):
+            val = float(line.split(":", 1)[1].strip())
+    return val if (src == h.hexdigest() and val is not None) else None
+
+
+def measure_extra(md, W, torch, name, evals, steps, adjoint=False):
+    """Forces-only and md_step throughput of one more workload (FP32 and FP64)."""
+    cfg = W.make(name)
+    N = cfg["pos"].shape[0]
+    dev = lambda a, dt=torch.float64: None if a is None else torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+    model = md.Model(cfg["model"])
+    cells = md.Cells()
+    multi = cfg["quat"] is not None
+    md.build_cells(model, cells, dev(cfg["pos"]), dev(cfg["quat"]), None, cfg["box"])
+    out = {"N": N, "box": cfg["box"].tolist(), "rc": cfg["model"]["rc"]}
+    ref = md.forces(model, cells, "fp64", torque=multi, per_molecule=False)
+    torch.cuda.synchronize()
+    P = int(ref["npairs"].item())
+    out["interacting_pairs"] = P
+    for prec in ("fp32", "fp64"):
+        buf = {"force": torch.empty((N, 3), dtype=torch.float64, device="cuda"),
+               "uw": torch.empty(5, dtype=torch.float64, device="cuda"),
+               "npairs": torch.empty(1, dtype=torch.int64, device="cuda")}
+        if multi:
+            buf["torque"] = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+        md.forces_into(model, cells, prec, buf)
+        torch.cuda.synchronize()
+        model.profile(True)
+        t = time.perf_counter()
+        for _ in range(evals):
+            md.forces_into(model, cells, prec, buf)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / evals
+        ms, k = model.profile_read("pair")
+        model.profile(False)
+        e = {"forces_interactions_per_s": P / wall, "forces_ms": 1e3 * wall, "pair_kernel_ms": ms / k}
+        if prec == "fp32":
+            F32, F64 = buf["force"], ref["force"]
+            e["force_rel_rms_vs_fp64"] = float(torch.linalg.norm(F32 - F64) / torch.linalg.norm(F64))
+            e["energy_rel_vs_fp64"] = abs(float(buf["uw"][0]) - float(ref["uw"][0])) / abs(float(ref["uw"][0]))
+        pos, vel, quat, ang = dev(cfg["pos"]), dev(cfg["vel"]), dev(cfg["quat"]), dev(cfg["angmom"])
+        md.step(model, cells, pos, vel, quat, ang, None, cfg["box"], cfg["dt"], 2, prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        md.step(model, cells, pos, vel, quat, ang, None, cfg["box"], cfg["dt"], steps, prec)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t
+        e.update({"steps_per_s": steps / ts, "step_interactions_per_s": P * steps / ts})
+        if adjoint:
+            md.build_cells(model, cells, dev(cfg["pos"]), dev(cfg["quat"]), None, cfg["box"])
+            md.forces_adjoint(model, cells, prec, 1.0, want_quat=multi)
+            torch.cuda.synchronize()
+            model.profile(True)
+            t = time.perf_counter()
+            for _ in range(evals):
+                md.forces_adjoint(model, cells, prec, 1.0, want_quat=multi)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t) / evals
+            ms, k = model.profile_read("adjoint")
+            model.profile(False)
+            e.update({"adjoint_ms": 1e3 * wall, "adjoint_interactions_per_s": P / wall})
+        out[prec] = e
+    out["fp32_speedup_forces"] = out["fp64"]["forces_ms"] / out["fp32"]["forces_ms"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +142,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="short run for profilers: few steps, no extras")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run 3 plain device copies of this many MiB (HBM byte-counter calibration)")
+    ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
@@ -68,7 +150,7 @@ def main():
         sys.exit(2)
     if args.quick:
         args.steps, args.warmup, args.force_evals = min(args.steps, 5), min(args.warmup, 2), 5
-        args.no_fp64 = args.no_cpu_baseline = True
+        args.no_fp64 = args.no_cpu_baseline = args.no_extra = True
 
     import torch
     from paper_1408_4599_amd import md, workloads as W
@@ -193,7 +275,8 @@ def main():
         "errors": errors,
         "nve_rel_energy_spread_fp32": float(np.abs(E - E[0]).max() / abs(E[0])),
         "roofline": {"bound": "alu", "achieved": W_alg / f32_pair / 1e12, "peak": PEAK_FP32 / 1e12,
-                     "unit": "TFLOP/s", "frac": W_alg / f32_pair / PEAK_FP32, "traffic": None,
+                     "unit": "TFLOP/s", "frac": W_alg / f32_pair / PEAK_FP32,
+                     "traffic": pair_traffic(["md_pair.hip", "md_device.h", "md_internal.h"]),
                      "kernel": "k_pair_lj1<float>" if model.single_site else "k_pair_ms<float>",
                      "algorithmic_flop_per_launch": W_alg,
                      "accounting": "8 FLOP per half-shell distance test (D) + 24 FLOP per unique interacting pair (P)",
@@ -205,6 +288,14 @@ def main():
                        "pair_kernel_ms": 1e3 * f64_pair,
                        "roofline_frac_fp64_peak": W_alg / f64_pair / PEAK_FP64}
         out["fp32_speedup_over_fp64"] = {"step": t64 / t32, "pair_kernel": f64_pair / f32_pair}
+
+    if not args.no_extra:
+        extra = {}
+        for name, ev, st, adj in (("c3_lj_slab_2m", 20, 20, False), ("c4_2cljq_500k", 10, 10, False),
+                                  ("c5_4site_200k", 10, 10, True)):
+            print(f"[bench] extra workload {name}", file=sys.stderr, flush=True)
+            extra[name] = measure_extra(md, W, torch, name, ev, st, adj)
+        out["workloads"] = extra
 
     # ---- oracle rows: FP32 errors on a sample and the CPU baseline ----
     if not args.no_cpu_baseline:
