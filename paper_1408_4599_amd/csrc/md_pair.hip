@@ -17,6 +17,9 @@
 // Every pair is evaluated from both ends (full shell), so no atomics are needed and results are
 // bitwise reproducible.  The pair work is VALU-bound (no dense contraction: no MFMA).
 
+#include <algorithm>
+#include <type_traits>
+
 #include "md_device.h"
 
 namespace mdcell {
@@ -162,38 +165,48 @@ __device__ __forceinline__ void write_partial_block(double *partial, double acc5
   }
 }
 
-// Quad-cell kernel with compaction.  A block of four wavefronts takes a 2 x 2 group of home
-// cells (x, y) in one z-layer; their 27-cell neighbourhoods together span 4 x 4 x 3 cells, which
-// are staged once into LDS (image shifts applied) in x-fastest order, so each wavefront's stencil
-// is nine contiguous x-rows of three cells.  In a wavefront, lanes = NI molecules x NS partner
-// slices (NI = 16, 32 or 64 from the home-cell occupancy) and lane (i, s) scans row entries
-// s, s + NS, ...: all molecule lanes of a slice read the same partner, so LDS reads broadcast.
-// Pass 1 runs only the exact FP64 cutoff test and appends hits to a per-lane list in LDS (a full
-// list evaluates further hits at once); pass 2 evaluates the interactions of the listed hits, so
-// the pair arithmetic runs for partners inside the cutoff only.  A tile that does not fit falls
-// back to lj1_cell_chunked for each home cell.
-constexpr int QCELLS = 48;  // 4 x 4 x 3 staged cells
+// Quad-cell kernel with compaction.  A block of four wavefronts takes 1 x 2 x 2 home cells (one in
+// x, two in y, two in z); their 27-cell neighbourhoods together span 3 x 4 x 4 cells, which are
+// staged once into LDS (image shifts applied) in x-fastest order.  In that order a wavefront's
+// stencil is three contiguous segments of nine cells (3 in x by 3 in y, one segment per z-layer).
+// In a wavefront with n home molecules, lane l < n NS (NS = min(8, floor(64 / n))) takes molecule
+// l % n and, in each segment, candidates s, s + NS, ... with s = l / n: all molecule lanes of a
+// slice read the same partner, so LDS reads broadcast.  Pass 1 runs only the exact FP64 cutoff
+// test and appends hits to a per-lane list in LDS; when a list could overflow, the listed hits are
+// evaluated (pass 2) and the lists restart, so the pair arithmetic runs for partners inside the
+// cutoff only.  A block whose tile exceeds the LDS capacity walks the same candidates in the same
+// order through per-wavefront windows of its segments, so its results are bitwise those of the
+// staged tile; flushes may come earlier, which does not change the order of any sum.  Slice sums
+// are combined through LDS in a fixed order.  Home cells with more than 64 molecules use
+// lj1_cell_chunked (a decision fixed by the configuration, not by the capacity).
+constexpr int QCELLS = 48;  // 3 x 4 x 4 staged cells
+constexpr int NSMAX = 8;
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double rc2, PairOut o, int cap, int lcap) {
   extern __shared__ double dyn[];
-  double *jx = dyn, *jy = dyn + cap, *jz = dyn + 2 * cap;
+  // staged positions, x y z interleaved: entry t at tp[3 t .. 3 t + 2]
+  double *tp = dyn;
+  // the same memory as an LDS-qualified pointer, so indexing stays 32-bit
+  __attribute__((address_space(3))) double *lds = (__attribute__((address_space(3))) double *)dyn;
   unsigned short *list = (unsigned short *)(dyn + 3 * cap);
   __shared__ int qoff[QCELLS + 1], qstart[QCELLS];
   __shared__ double qsh[QCELLS][3];
+  __shared__ int scnt[4][64];
   __shared__ NbTable nb;
   __shared__ double red[4][5];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nbx = (c.nx + 1) >> 1, nby = (c.ny + 1) >> 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int nby = (c.ny + 1) >> 1, nbz = (c.nz + 1) >> 1;
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (b < nbx * nby * c.nz) {
-    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
-    // tile cell u = ux + 4 uy + 16 uz covers cell (2 bx - 1 + ux, 2 by - 1 + uy, bz - 1 + uz)
+  if (b < c.nx * nby * nbz) {
+    const int bx = b % c.nx, by = (b / c.nx) % nby, bz = b / (c.nx * nby);
+    // tile cell u = ux + 3 uy + 12 uz covers cell (bx - 1 + ux, 2 by - 1 + uy, 2 bz - 1 + uz)
     if (tid < 64) {
       int cnt = 0;
       if (tid < QCELLS) {
-        int x = 2 * bx - 1 + (tid & 3), y = 2 * by - 1 + ((tid >> 2) & 3), z = bz - 1 + (tid >> 4);
+        int x = bx - 1 + tid % 3, y = 2 * by - 1 + (tid / 3) % 4, z = 2 * bz - 1 + tid / 12;
         double shx = 0.0, shy = 0.0, shz = 0.0;
         if (x < 0) x += c.nx, shx = -c.Lx;
         else if (x >= c.nx) x -= c.nx, shx = c.Lx;
@@ -213,101 +226,186 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
     }
     __syncthreads();
     const int U = qoff[QCELLS];
-    // this wavefront's home cell
-    const int hx = wave & 1, hy = wave >> 1;
-    const int cx = 2 * bx + hx, cy = 2 * by + hy;
-    const bool hvalid = cx < c.nx && cy < c.ny;
-    const int hcell = hvalid ? (bz * c.ny + cy) * c.nx + cx : 0;
-    const int hs = hvalid ? c.cell_start[hcell] : 0;
-    const int hn = hvalid ? c.cell_start[hcell + 1] - hs : 0;
-    const int bad = (U > cap) || (hn > 64);
-    if (!__syncthreads_or(bad)) {
-      for (int t = tid; t < U; t += 256) {
-        int lo = 0, hi = QCELLS;  // last tile cell with qoff <= t
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (qoff[mid] <= t) lo = mid;
-          else hi = mid;
-        }
-        const int src = qstart[lo] + (t - qoff[lo]);
-        jx[t] = c.sx[src] + qsh[lo][0];
-        jy[t] = c.sy[src] + qsh[lo][1];
-        jz[t] = c.sz[src] + qsh[lo][2];
-      }
-      __syncthreads();
-      if (hn > 0) {
-        const int NI = hn <= 16 ? 16 : (hn <= 32 ? 32 : 64);
-        const int NS = 64 / NI;
-        const int il = lane & (NI - 1), sl = lane / NI;
-        const bool act = il < hn;
-        const int self = qoff[(hx + 1) + 4 * (hy + 1) + 16] + il;
-        unsigned short *mylist = list + (size_t)wave * 64 * lcap + lane;
-        LJAcc<R> a;
-        const R eps24 = (R)p.eps24, sig2 = (R)p.sig2;
-        if (act) {
-          const double xi = jx[self], yi = jy[self], zi = jz[self];
-          int cnt = 0;
-          for (int r = 0; r < 9; ++r) {
-            const int u0 = hx + 4 * (hy + r % 3) + 16 * (r / 3);
-            const int lo = qoff[u0], hi = qoff[u0 + 3];
-            int t = lo + sl;
-            for (; t + NS < hi; t += 2 * NS) {
-              const int t2 = t + NS;
-              const double ax = xi - jx[t], ay = yi - jy[t], az = zi - jz[t];
-              const double bx_ = xi - jx[t2], by_ = yi - jy[t2], bz_ = zi - jz[t2];
-              const double ra = fma(az, az, fma(ay, ay, ax * ax));
-              const double rb = fma(bz_, bz_, fma(by_, by_, bx_ * bx_));
-              if (ra < rc2 && t != self) {
-                if (cnt < lcap) mylist[64 * cnt++] = (unsigned short)t;
-                else a.add(ax, ay, az, ra, eps24, sig2, p.eps4, p.sig2);
-              }
-              if (rb < rc2 && t2 != self) {
-                if (cnt < lcap) mylist[64 * cnt++] = (unsigned short)t2;
-                else a.add(bx_, by_, bz_, rb, eps24, sig2, p.eps4, p.sig2);
-              }
-            }
-            if (t < hi) {
-              const double ax = xi - jx[t], ay = yi - jy[t], az = zi - jz[t];
-              const double ra = fma(az, az, fma(ay, ay, ax * ax));
-              if (ra < rc2 && t != self) {
-                if (cnt < lcap) mylist[64 * cnt++] = (unsigned short)t;
-                else a.add(ax, ay, az, ra, eps24, sig2, p.eps4, p.sig2);
-              }
-            }
-          }
-          for (int k = 0; k < cnt; ++k) {
-            const int u = mylist[64 * k];
-            const double dx = xi - jx[u], dy = yi - jy[u], dz = zi - jz[u];
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            a.add(dx, dy, dz, r2, eps24, sig2, p.eps4, p.sig2);
+    // this wavefront's home cell: tile cell uh (unshifted, since it lies inside the box)
+    const int hy = wave & 1, hz = wave >> 1;
+    const bool hvalid = 2 * by + hy < c.ny && 2 * bz + hz < c.nz;
+    const int uh = 1 + 3 * (hy + 1) + 12 * (hz + 1);
+    const int hn = hvalid ? __builtin_amdgcn_readfirstlane(qoff[uh + 1] - qoff[uh]) : 0;
+    const int hs = qstart[uh];
+    if (!__syncthreads_or(hn > 64)) {
+      // the walk reads up to 2 NS - 1 <= 15 entries past a segment (results discarded), so the
+      // tile needs that much slack
+      const bool tiled = U + 16 <= cap;  // block-uniform
+      // the permutation entry of this lane's home molecule, needed only at the end
+      const int orig = lane < hn ? c.perm[hs + lane] : 0;
+      if (tiled) {
+        // stage by x-rows of three cells (contiguous in the sorted arrays unless x wraps): wave w
+        // takes rows w, w + 4, w + 8, w + 12, first entries of all four rows loaded together
+        double vx[4], vy[4], vz[4];
+        int dst[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int u = 3 * (wave + 4 * q);
+          const int e = qoff[u] + lane;
+          dst[q] = -1;
+          if (e < qoff[u + 3]) {
+            const int cc = e < qoff[u + 1] ? u : (e < qoff[u + 2] ? u + 1 : u + 2);
+            const int src = qstart[cc] + (e - qoff[cc]);
+            vx[q] = c.sx[src] + qsh[cc][0], vy[q] = c.sy[src] + qsh[cc][1], vz[q] = c.sz[src] + qsh[cc][2];
+            dst[q] = e;
           }
         }
 #pragma unroll
-        for (int off = 16; off < 64; off <<= 1) {
-          if (off >= NI) {
-            a.fx += __shfl_xor(a.fx, off), a.fy += __shfl_xor(a.fy, off), a.fz += __shfl_xor(a.fz, off);
-            a.u += __shfl_xor(a.u, off);
-            a.wx += __shfl_xor(a.wx, off), a.wy += __shfl_xor(a.wy, off), a.wz += __shfl_xor(a.wz, off);
-            a.n += __shfl_xor(a.n, off);
+        for (int q = 0; q < 4; ++q)
+          if (dst[q] >= 0) tp[3 * dst[q]] = vx[q], tp[3 * dst[q] + 1] = vy[q], tp[3 * dst[q] + 2] = vz[q];
+        for (int q = 0; q < 4; ++q) {  // rows longer than 64 entries
+          const int u = 3 * (wave + 4 * q);
+          for (int e = qoff[u] + 64 + lane; e < qoff[u + 3]; e += 64) {
+            const int cc = e < qoff[u + 1] ? u : (e < qoff[u + 2] ? u + 1 : u + 2);
+            const int src = qstart[cc] + (e - qoff[cc]);
+            tp[3 * e] = c.sx[src] + qsh[cc][0], tp[3 * e + 1] = c.sy[src] + qsh[cc][1];
+            tp[3 * e + 2] = c.sz[src] + qsh[cc][2];
           }
         }
-        if (act && sl == 0) {
-          const int orig = c.perm[hs + il];
-          a.u -= (double)a.n * p.shift;
-          o.force[3 * orig] = a.fx, o.force[3 * orig + 1] = a.fy, o.force[3 * orig + 2] = a.fz;
-          if (o.torque) o.torque[3 * orig] = 0.0, o.torque[3 * orig + 1] = 0.0, o.torque[3 * orig + 2] = 0.0;
-          if (o.u_mol) o.u_mol[orig] = 0.5 * a.u;
-          if (o.w_mol) o.w_mol[orig] = 0.5 * (a.wx + a.wy + a.wz);
-          if (o.nnb_mol) o.nnb_mol[orig] = a.n;
-          acc5[0] = 0.5 * a.u, acc5[1] = 0.5 * a.wx, acc5[2] = 0.5 * a.wy, acc5[3] = 0.5 * a.wz;
-          acc5[4] = (double)a.n;
+        __syncthreads();
+      }
+      LJAcc<R> a;
+      const int NS = hn > 0 ? min(NSMAX, 64 / hn) : 1;
+      const int il = hn > 0 ? lane % hn : 0, sl = hn > 0 ? lane / hn : NS;
+      const bool act = sl < NS;
+      if (hn > 0) {
+        const int self = qoff[uh] + il;
+        double xi = 1e30, yi = 1e30, zi = 1e30;  // idle lanes: no candidate is within the cutoff
+        if (act) {
+          if (tiled) xi = tp[3 * self], yi = tp[3 * self + 1], zi = tp[3 * self + 2];
+          else xi = c.sx[hs + il], yi = c.sy[hs + il], zi = c.sz[hs + il];
         }
+        unsigned short *wlist = list + (size_t)wave * 64 * lcap;
+        const R eps24 = (R)p.eps24, sig2 = (R)p.sig2;
+        // staged positions: the whole tile (slot = tile index) or this wavefront's window of cq
+        // entries, of which the first C are staged at a time
+        const int cq = (cap - 16) >> 2;
+        const int C = (cq - 16) / (2 * NS) * (2 * NS);
+        const int wb = tiled ? 0 : 3 * wave * cq;  // index into dyn of staged slot 0 (32-bit LDS math)
+        int cnt = 0;
+        // pass 2: the hits of a molecule (its NS lanes' lists, in slice order) are split into NS
+        // contiguous equal parts, one per lane; each lane sums its part in order
+        auto flush = [&]() {
+          scnt[wave][lane] = cnt;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (act) {
+            int H = 0;
+            for (int s2 = 0; s2 < NS; ++s2) H += scnt[wave][il + s2 * hn];
+            const int q0 = H * sl / NS, q1 = H * (sl + 1) / NS;
+            int sp = 0, j = q0, csp = scnt[wave][il];
+            for (int q = q0; q < q1; ++q, ++j) {
+              while (j >= csp) j -= csp, ++sp, csp = scnt[wave][il + sp * hn];
+              const int u = wlist[il + sp * hn + 64 * j];
+              const int iu = wb + 3 * u;
+              const double dx = xi - lds[iu], dy = yi - lds[iu + 1], dz = zi - lds[iu + 2];
+              const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+              a.add(dx, dy, dz, r2, eps24, sig2, p.eps4, p.sig2);
+            }
+          }
+          cnt = 0;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        };
+        unsigned short *mylist = wlist + lane;
+        const int sla = act ? sl : 0;  // idle lanes walk with slice 0
+        for (int d = 0; d < 3; ++d) {
+          const int u0 = 3 * hy + 12 * (hz + d);
+          const int lo = __builtin_amdgcn_readfirstlane(qoff[u0]), hi = __builtin_amdgcn_readfirstlane(qoff[u0 + 9]);
+          for (int cs = lo, ce; cs < hi; cs = ce) {
+            ce = tiled ? hi : min(hi, cs + C);
+            const int off = tiled ? 0 : cs;
+            if (!tiled) {
+              // stage [cs, ce) of this segment into the window; the previous window is flushed
+              flush();
+              for (int k = cs + lane; k < ce; k += 64) {
+                int u = u0;
+                while (k >= qoff[u + 1]) ++u;
+                const int src = qstart[u] + (k - qoff[u]);
+                double *e = dyn + wb + 3 * (k - cs);
+                e[0] = c.sx[src] + qsh[u][0];
+                e[1] = c.sy[src] + qsh[u][1];
+                e[2] = c.sz[src] + qsh[u][2];
+              }
+              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+              __builtin_amdgcn_wave_barrier();
+              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            // two candidates per iteration, both loaded before either is tested.  Only the last
+            // iteration can pass the end of the range (its extra slots are read, never counted),
+            // and only the home layer holds the molecule itself.
+            auto walk = [&](auto tail, auto home) {
+              int ia = wb + 3 * (cs + sla - off);  // running LDS index of candidate a
+              for (int kb = cs; tail ? kb < ce : kb + 2 * NS <= ce; kb += 2 * NS, ia += 6 * NS) {
+                const int ta = kb + sla, tb = ta + NS;
+                const int sa = ta - off, sb = tb - off;
+                const int ib = ia + 3 * NS;
+                const double ax = xi - lds[ia], ay = yi - lds[ia + 1], az = zi - lds[ia + 2];
+                const double bx_ = xi - lds[ib], by_ = yi - lds[ib + 1], bz_ = zi - lds[ib + 2];
+                const double ra = fma(az, az, fma(ay, ay, ax * ax));
+                const double rb = fma(bz_, bz_, fma(by_, by_, bx_ * bx_));
+                bool ha = ra < rc2, hb = rb < rc2;
+                if (tail) ha = ha && ta < ce, hb = hb && tb < ce;
+                if (home) ha = ha && ta != self, hb = hb && tb != self;
+                // the slot is always written; the count advances on a hit
+                mylist[64 * cnt] = (unsigned short)sa;
+                cnt += ha ? 1 : 0;
+                mylist[64 * cnt] = (unsigned short)sb;
+                cnt += hb ? 1 : 0;
+                if (__any(cnt > lcap - 2)) flush();
+                if (tail) break;
+              }
+            };
+            const int cfull = cs + (ce - cs) / (2 * NS) * (2 * NS);
+            if (d == 1) walk(std::false_type(), std::true_type());
+            else walk(std::false_type(), std::false_type());
+            if (cfull < ce) {
+              const int cs0 = cs;
+              cs = cfull;
+              if (d == 1) walk(std::true_type(), std::true_type());
+              else walk(std::true_type(), std::false_type());
+              cs = cs0;
+            }
+          }
+        }
+        flush();
+      }
+      // combine the slices of each molecule in a fixed order through LDS (the tile is free now)
+      __syncthreads();
+      double *sred = dyn + (size_t)wave * 64 * 8;
+      if (act) {
+        double *e = sred + lane;  // [quantity][lane]: consecutive lanes, distinct banks
+        e[0] = a.fx, e[64] = a.fy, e[128] = a.fz, e[192] = a.u, e[256] = a.wx, e[320] = a.wy, e[384] = a.wz;
+        e[448] = (double)a.n;
+      }
+      __syncthreads();
+      if (lane < hn) {
+        double v[8];
+        for (int q = 0; q < 8; ++q) v[q] = sred[q * 64 + lane];
+        for (int s = 1; s < NS; ++s)
+          for (int q = 0; q < 8; ++q) v[q] += sred[q * 64 + lane + s * hn];
+        const double nn = v[7];
+        const double u = v[3] - nn * p.shift;
+        o.force[3 * orig] = v[0], o.force[3 * orig + 1] = v[1], o.force[3 * orig + 2] = v[2];
+        if (o.torque) o.torque[3 * orig] = 0.0, o.torque[3 * orig + 1] = 0.0, o.torque[3 * orig + 2] = 0.0;
+        if (o.u_mol) o.u_mol[orig] = 0.5 * u;
+        if (o.w_mol) o.w_mol[orig] = 0.5 * (v[4] + v[5] + v[6]);
+        if (o.nnb_mol) o.nnb_mol[orig] = (int)nn;
+        acc5[0] = 0.5 * u, acc5[1] = 0.5 * v[4], acc5[2] = 0.5 * v[5], acc5[3] = 0.5 * v[6], acc5[4] = nn;
       }
     } else {
       for (int w = 0; w < 4; ++w) {
-        const int fx = 2 * bx + (w & 1), fy = 2 * by + (w >> 1);
-        if (fx < c.nx && fy < c.ny)
-          lj1_cell_chunked<R>(c, p, rc2, o, (bz * c.ny + fy) * c.nx + fx, jx, jy, jz, cap, nb, acc5);
+        const int fy = 2 * by + (w & 1), fz = 2 * bz + (w >> 1);
+        if (fy < c.ny && fz < c.nz)
+          lj1_cell_chunked<R>(c, p, rc2, o, (fz * c.ny + fy) * c.nx + bx, dyn, dyn + cap, dyn + 2 * cap, cap, nb,
+                              acc5);
       }
     }
   }
@@ -319,20 +417,21 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
 // are 16-bit staged indices, so the cap stays below 65536.)
 inline int lj1_tile_cap(int64_t N, int64_t ncell) {
   const double mean = (double)N / (double)ncell;
-  int cap = (int)(QCELLS * mean * 1.3) + 64;
-  cap = (cap + 63) / 64 * 64;
+  int cap = (int)(QCELLS * mean * 1.12) + 32;
+  cap = (cap + 31) / 32 * 32;
   return cap < 256 ? 256 : (cap > 4096 ? 4096 : cap);
 }
 
 // Per-lane hit-list length: expected partners per molecule (4/3 pi r_c^3 N/V) over the slices of
-// a lane, with margin; hits beyond it are evaluated inline.
+// a lane, with margin; fuller lists are flushed early (pass 2) and restarted.
 inline int lj1_list_cap(int64_t N, double V, double rc, int64_t ncell) {
   const double mean = (double)N / (double)ncell;
-  const int NS = mean <= 16.0 ? 4 : (mean <= 32.0 ? 2 : 1);
+  int NS = (int)(64.0 / (mean > 1.0 ? mean : 1.0));
+  NS = NS < 1 ? 1 : (NS > NSMAX ? NSMAX : NS);
   const double hits = 4.18879020478639 * rc * rc * rc * (double)N / V / NS;
-  int l = (int)(1.4 * hits) + 8;
+  int l = (int)(1.25 * hits) + 4;
   l = (l + 7) / 8 * 8;
-  return l < 16 ? 16 : (l > 96 ? 96 : l);
+  return l < 16 ? 16 : (l > 64 ? 64 : l);
 }
 
 // =====================================================================================
@@ -630,10 +729,11 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
   const bool f32 = precision == MD_FP32;
   if (m->single_site) {
     const LJPair p = m->host.lj[0][0][0][0];
-    const int cap = lj1_tile_cap(c->N, c->ncell);
+    const int cap = std::max(lj1_tile_cap(c->N, c->ncell), 256 * 8 / 3 + 1);
     const int lcap = lj1_list_cap(c->N, c->box[0] * c->box[1] * c->box[2], m->host.rc, c->ncell);
-    const size_t lds = (size_t)cap * 3 * sizeof(double) + (size_t)lcap * 256 * sizeof(unsigned short);
-    const int64_t nq = pair_blocks((int64_t)((c->nc[0] + 1) / 2) * ((c->nc[1] + 1) / 2) * c->nc[2]);
+    const size_t lds = std::max((size_t)cap * 3 * sizeof(double), (size_t)256 * 8 * sizeof(double)) +
+                       (size_t)lcap * 256 * sizeof(unsigned short);
+    const int64_t nq = pair_blocks((int64_t)c->nc[0] * ((c->nc[1] + 1) / 2) * ((c->nc[2] + 1) / 2));
     *nblocks = nq;
     if (f32) k_pair_lj1<float><<<(unsigned)nq, 256, lds, s>>>(cd, p, m->host.rc2, o, cap, lcap);
     else k_pair_lj1<double><<<(unsigned)nq, 256, lds, s>>>(cd, p, m->host.rc2, o, cap, lcap);

@@ -177,7 +177,7 @@ def c2_lj_1m():
     return homogeneous_lj(64, 0.75, 0.9, rc=2.5, shift=True, seed=2, name="c2_lj_1m", nsteps=1000)
 
 
-def c3_lj_slab_2m(N_total=2_000_000):
+def c3_lj_slab_2m(N_total=2_000_000, name="c3_lj_slab_2m"):
     """Planar vapour-liquid interface: box 3L x L x L with rho_avg * 3L^3 = N, liquid slab
     (rho = 0.73, FCC with random vacancies) in the middle third along x, vapour (rho = 0.02,
     uniform, no two molecules closer than 1 sigma) elsewhere; T = 0.85, r_c = 3 (shifted)."""
@@ -194,7 +194,13 @@ def c3_lj_slab_2m(N_total=2_000_000):
     vap = _vapour(rng, n_vap, L, liq)
     pos = np.concatenate([liq, vap], axis=0)
     perm = rng.permutation(pos.shape[0])
-    return _system("c3_lj_slab_2m", lj_model(3.0, True), pos[perm], [3 * L, L, L], 0.85, rng, 0.002, 1000)
+    return _system(name, lj_model(3.0, True), pos[perm], [3 * L, L, L], 0.85, rng, 0.002, 1000)
+
+
+def c3_small():
+    """The slab of c3_lj_slab_2m at N = 12 000 (box 75 x 25 x 25): liquid neighbourhoods hold far
+    more molecules than the box average, as in the full-size slab."""
+    return c3_lj_slab_2m(12_000, "c3_small")
 
 
 def _vapour(rng, n, L, liq, dmin=1.0):
@@ -333,6 +339,7 @@ CONFIGS = {
     "c5_4site_200k": c5_four_site,
     "c4_small": c4_small,
     "c5_small": c5_small,
+    "c3_small": c3_small,
     "mixture_small": mixture_small,
 }
 
