@@ -130,13 +130,15 @@ __device__ __forceinline__ int find_nb(const int *off, int g) {
 // Energy per unit moment product of one electrostatic site pair and its partial derivatives
 // with respect to r and the cosines c_i = e_a.rhat, c_j = e_b.rhat, c_ij = e_a.e_b (rhat points
 // from site b of molecule j to site a of molecule i).  ir = 1/r; krc3 = kappa / r_c^3.
+// Per unit moment product: energy t (t0: the same without the reaction-field term) and its
+// partial derivatives with respect to r, c_i, c_j and c_ij.
 template <typename R> struct Unit {
-  R t, tr, ti, tj, tij;
+  R t, tr, ti, tj, tij, t0;
 };
 
 template <int KA, int KB, typename R>
 __device__ __forceinline__ Unit<R> unit_terms(R ir, R ci, R cj, R cij, R krc3) {
-  Unit<R> u{0, 0, 0, 0, 0};
+  Unit<R> u{0, 0, 0, 0, 0, 0};
   const R ir2 = ir * ir, ir3 = ir2 * ir, ir4 = ir3 * ir;
   if constexpr (KA == KIND_CHG && KB == KIND_CHG) {
     u.t = ir;
@@ -159,6 +161,7 @@ __device__ __forceinline__ Unit<R> unit_terms(R ir, R ci, R cj, R cij, R krc3) {
     u.ti = (R)3 * ci * ir3;
   } else if constexpr (KA == KIND_DIP && KB == KIND_DIP) {
     const R g = fma((R)-3 * ci, cj, cij);
+    u.t0 = g * ir3;
     u.t = fma(g, ir3, -krc3 * cij);
     u.tr = (R)-3 * g * ir4;
     u.ti = (R)-3 * cj * ir3;
@@ -190,6 +193,7 @@ __device__ __forceinline__ Unit<R> unit_terms(R ir, R ci, R cj, R cij, R krc3) {
     u.tj = p * ((R)-10 * cj - (R)30 * cj * ci2 - (R)20 * ci * s);
     u.tij = p * (R)4 * s;
   }
+  if constexpr (!(KA == KIND_DIP && KB == KIND_DIP)) u.t0 = u.t;
   return u;
 }
 

@@ -445,15 +445,18 @@ template <typename R> __device__ __forceinline__ void cross_acc(R *T, const R *a
   T[2] += a[0] * f[1] - a[1] * f[0];
 }
 
-// Accumulators of one molecule pair (seen from molecule i).
+// Accumulators of one molecule pair (seen from molecule i).  The energy is summed in FP64 from
+// FP64 parameters (mixed LJ parameters, moment products, the reaction-field factor), so that their
+// rounding to R leaves no systematic error in U.
 template <typename R> struct PairAcc {
-  R F[3], T[3], u;
+  R F[3], T[3];
+  double u;
 };
 
 // One electrostatic site pair: site a of i (offset oa, axis ea) and site b of j (ob, eb).
 template <int KA, int KB, typename R>
-__device__ __forceinline__ void elec_site(R pm, const R *oa, const R *ea, const R *ob, const R *eb, R dx, R dy, R dz,
-                                          R krc3, PairAcc<R> &acc) {
+__device__ __forceinline__ void elec_site(R pm, double pmd, const R *oa, const R *ea, const R *ob, const R *eb, R dx,
+                                          R dy, R dz, R krc3, double krc3d, PairAcc<R> &acc) {
   const R rx = dx + oa[0] - ob[0], ry = dy + oa[1] - ob[1], rz = dz + oa[2] - ob[2];
   const R r2 = fma(rz, rz, fma(ry, ry, rx * rx));
   const R ir = rsq_nr<R>(r2);
@@ -482,13 +485,16 @@ __device__ __forceinline__ void elec_site(R pm, const R *oa, const R *ea, const 
     }
     cross_acc(acc.T, ea, ga);  // tau -= e_a x dU/de_a
   }
-  acc.u += pm * t.t;
+  double ue = (double)t.t0;
+  if constexpr (KA == KIND_DIP && KB == KIND_DIP) ue = fma(-krc3d, (double)cij, ue);
+  acc.u = fma(pmd, ue, acc.u);
 }
 
 // All electrostatic site pairs of kinds (KA on i, KB on j).
+// vi: all site vectors of i; vj: the electrostatic site vectors of j (slots from SL on).
 template <int KA, int KB, int SL, int SC, int SD, int SQ, bool MIX, typename R>
 __device__ __forceinline__ void elec_group(const CompDev &A, const CompDev &B, const R (*vi)[3], const R *vj,
-                                           R dx, R dy, R dz, R krc3, PairAcc<R> &acc) {
+                                           R dx, R dy, R dz, R krc3, double krc3d, PairAcc<R> &acc) {
   using S = Slots<SL, SC, SD, SQ>;
   constexpr int NA = KA == KIND_CHG ? SC : (KA == KIND_DIP ? SD : SQ);
   constexpr int NB = KB == KIND_CHG ? SC : (KB == KIND_DIP ? SD : SQ);
@@ -501,167 +507,249 @@ __device__ __forceinline__ void elec_group(const CompDev &A, const CompDev &B, c
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
     if (a >= na) break;
-    const R ma = (R)(KA == KIND_CHG ? A.chg_q[a] : (KA == KIND_DIP ? A.dip_mu[a] : A.quad_Q[a]));
+    const double mad = KA == KIND_CHG ? A.chg_q[a] : (KA == KIND_DIP ? A.dip_mu[a] : A.quad_Q[a]);
+    const R ma = (R)mad;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       if (b >= nb) break;
-      const R mb = (R)(KB == KIND_CHG ? B.chg_q[b] : (KB == KIND_DIP ? B.dip_mu[b] : B.quad_Q[b]));
-      elec_site<KA, KB, R>(ma * mb, vi[OA + a], vi[EA + a], vj + 3 * (OB + b), vj + 3 * (EB + b), dx, dy, dz,
-                           krc3, acc);
+      const double mbd = KB == KIND_CHG ? B.chg_q[b] : (KB == KIND_DIP ? B.dip_mu[b] : B.quad_Q[b]);
+      elec_site<KA, KB, R>(ma * (R)mbd, mad * mbd, vi[OA + a], vi[EA + a], vj + 3 * (OB - SL + b),
+                           vj + 3 * (EB - SL + b), dx, dy, dz, krc3, krc3d, acc);
     }
   }
 }
 
+// One molecule pair seen from i: d = r_i - r_j (FP64, image shift applied).  LJ site separations
+// and energies are formed in FP64 from the FP64 site offsets (vil, vjl); the LJ force scalar and
+// all electrostatic terms are evaluated in R from the site vectors vi and vje (electrostatic slots
+// of j).  gfx950 issues FP64 adds and fmas at the FP32 rate, so only the reciprocals and the
+// multipole polynomials gain from R = float.
 template <int SL, int SC, int SD, int SQ, bool MIX, typename R>
-__device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci, int cj, const R (*vi)[3],
-                                         const R *vj, R dx, R dy, R dz, PairAcc<R> &acc) {
+__device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci, int cj, const double (*vil)[3],
+                                         const R (*vi)[3], const double *vjl, const R *vje, double dxd, double dyd,
+                                         double dzd, PairAcc<R> &acc) {
   const CompDev &A = md->comp[ci];
   const CompDev &B = md->comp[cj];
   const int nla = MIX ? A.n_lj : SL, nlb = MIX ? B.n_lj : SL;
 #pragma unroll
   for (int a = 0; a < SL; ++a) {
     if (a >= nla) break;
+    const double ax = dxd + vil[a][0], ay = dyd + vil[a][1], az = dzd + vil[a][2];
 #pragma unroll
     for (int b = 0; b < SL; ++b) {
       if (b >= nlb) break;
       const LJPair &p = md->lj[ci][cj][a][b];
-      const R *ob = vj + 3 * b;
-      const R rx = dx + vi[a][0] - ob[0], ry = dy + vi[a][1] - ob[1], rz = dz + vi[a][2] - ob[2];
-      const R r2 = fma(rz, rz, fma(ry, ry, rx * rx));
-      const R ir2 = rcp_nr<R>(r2);
+      const double rx = ax - vjl[3 * b], ry = ay - vjl[3 * b + 1], rz = az - vjl[3 * b + 2];
+      const double r2 = fma(rz, rz, fma(ry, ry, rx * rx));
+      // force scalar in R (FP32: one hardware reciprocal, 1 ulp)
+      R ir2;
+      if constexpr (sizeof(R) == 4) ir2 = __builtin_amdgcn_rcpf((float)r2);
+      else ir2 = rcp_nr<double>(r2);
       const R s2 = (R)p.sig2 * ir2;
       const R s6 = s2 * s2 * s2;
-      acc.u += ((R)p.eps4 * s6) * (s6 - (R)1);  // shift summed per molecule pair in FP64
       const R fs = ((R)p.eps24 * ir2) * (s6 * fma((R)2, s6, (R)-1));
-      const R f[3] = {fs * rx, fs * ry, fs * rz};
+      // energy in FP64 (the shift is summed per molecule pair)
+      const double ir2d = rcp_fp64_from<R>(r2);
+      const double s2d = p.sig2 * ir2d;
+      const double s6d = s2d * s2d * s2d;
+      acc.u = fma(p.eps4 * s6d, s6d - 1.0, acc.u);
+      const R f[3] = {fs * (R)rx, fs * (R)ry, fs * (R)rz};
       acc.F[0] += f[0], acc.F[1] += f[1], acc.F[2] += f[2];
       cross_acc(acc.T, vi[a], f);
     }
   }
+  const R dx = (R)dxd, dy = (R)dyd, dz = (R)dzd;
+  const R *vj = vje;
   if constexpr (SC + SD + SQ > 0) {
-    const R krc3 = (R)md->kappa_rc3;
+    const double krc3d = md->kappa_rc3;
+    const R krc3 = (R)krc3d;
     if constexpr (SC > 0) {
-      elec_group<KIND_CHG, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+      elec_group<KIND_CHG, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
       if constexpr (SD > 0) {
-        elec_group<KIND_CHG, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
-        elec_group<KIND_DIP, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+        elec_group<KIND_CHG, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
+        elec_group<KIND_DIP, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
       }
       if constexpr (SQ > 0) {
-        elec_group<KIND_CHG, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
-        elec_group<KIND_QUAD, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+        elec_group<KIND_CHG, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
+        elec_group<KIND_QUAD, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
       }
     }
     if constexpr (SD > 0) {
-      elec_group<KIND_DIP, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+      elec_group<KIND_DIP, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
       if constexpr (SQ > 0) {
-        elec_group<KIND_DIP, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
-        elec_group<KIND_QUAD, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+        elec_group<KIND_DIP, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
+        elec_group<KIND_QUAD, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
       }
     }
-    if constexpr (SQ > 0) elec_group<KIND_QUAD, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, acc);
+    if constexpr (SQ > 0)
+      elec_group<KIND_QUAD, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
   }
 }
 
-template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP>
-__global__ __launch_bounds__(64) void k_pair_ms(CellsDev c, const ModelDev *__restrict__ md, double rc2, PairOut o) {
+// One block of W wavefronts per home cell.  The 27-cell neighbourhood is staged through LDS in
+// windows of CAP molecules shared by the block (COM position in FP64, LJ site offsets in FP64,
+// electrostatic site vectors in R, component id); the home molecules are split evenly over the
+// wavefronts, and in a wavefront with n of them lanes are n molecules x NS partner slices
+// (NS = min(8, floor(64 / n))).  Pass 1 runs the exact FP64 COM cutoff test and appends hits
+// (window slots, one byte) to per-lane lists; pass 2 evaluates the listed molecule pairs, the hits
+// of each molecule (its NS lanes' lists in slice order) split into NS contiguous equal parts.
+// Slices are combined with cross-lane reads in a fixed order.  A home cell with more than 64 W
+// molecules is taken 64 W at a time.
+template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 : 3))) void k_pair_ms(CellsDev c, const ModelDev *__restrict__ md, double rc2,
+                                                    PairOut o) {
   constexpr int NV = Slots<SL, SC, SD, SQ>::nv;
-  __shared__ double jx[CAP], jy[CAP], jz[CAP];
-  __shared__ R jv[CAP][NV * 3];
+  constexpr int NE = NV - SL > 0 ? NV - SL : 1;  // electrostatic slots
+  constexpr int LCAP = 32;
+  static_assert(CAP <= 256, "list entries are bytes");
+  __shared__ double jp[CAP * 3 + 48];  // slack: the walk reads up to 2 NS - 1 slots past the window
+  __shared__ double jl[CAP][SL * 3];   // LJ site offsets (FP64)
+  __shared__ R jv[CAP][NE * 3];        // electrostatic site offsets and axes
   __shared__ int jc_[MIX ? CAP : 1];
+  __shared__ unsigned char lists[W][LCAP * 64];
+  __shared__ int scnts[W][64];
   __shared__ NbTable nb;
-  const int lane = threadIdx.x;
+  __shared__ double red[W][5];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  unsigned char *list = lists[wave];
+  int *scnt = scnts[wave];
   const int cell = xcd_remap(blockIdx.x, gridDim.x);
-  double bu = 0.0, bwx = 0.0, bwy = 0.0, bwz = 0.0, bn = 0.0;
+  double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int hs = cell < c.ncell ? c.cell_start[cell] : 0;
-  const int hn = cell < c.ncell ? c.cell_start[cell + 1] - hs : 0;
+  const int hn = cell < c.ncell ? __builtin_amdgcn_readfirstlane(c.cell_start[cell + 1] - hs) : 0;
   if (hn > 0) {
-    build_nb(c, cell, nb);
+    if (tid < 64) build_nb(c, cell, nb);
     __syncthreads();
     const int M = nb.off[27];
     const int self0 = nb.off[13];
-    const int NI = hn <= 16 ? 16 : (hn <= 32 ? 32 : 64);
-    const int NS = 64 / NI;
-    const int il = lane & (NI - 1), sl = lane / NI;
-    for (int ic = 0; ic < hn; ic += 64) {
-      const int iloc = ic + il;
-      const bool act = iloc < hn;
-      double xi = 0.0, yi = 0.0, zi = 0.0;
+    for (int ic = 0; ic < hn; ic += 64 * W) {
+      // this round's molecules, split evenly over the wavefronts (wave-uniform)
+      const int rem = min(64 * W, hn - ic), base = rem / W, extra = rem % W;
+      const int hc = base + (wave < extra ? 1 : 0);
+      const int i0 = ic + wave * base + min(wave, extra);
+      const int NS = hc > 0 ? min(8, 64 / hc) : 1;
+      const int il = hc > 0 ? lane % hc : 0, sl = hc > 0 ? lane / hc : NS;
+      const bool act = sl < NS;
+      const int sla = act ? sl : 0;
+      const int iloc = i0 + il;
+      double xi = 1e30, yi = 1e30, zi = 1e30;  // idle lanes: no candidate is within the cutoff
       R vi[NV][3];
+      double vil[SL][3];
       int ci = 0;
-      if (act) {
-        const int s = hs + iloc;
-        xi = c.sx[s], yi = c.sy[s], zi = c.sz[s];
-        if (MIX) ci = c.scomp[s];
-        const double *v = c.svec + (int64_t)s * NV * 3;
+      {
+        const int sidx = hs + (hc > 0 ? iloc : 0);
+        if (act) xi = c.sx[sidx], yi = c.sy[sidx], zi = c.sz[sidx];
+        if (MIX) ci = c.scomp[sidx];
+        const double *v = c.svec + (int64_t)sidx * NV * 3;
 #pragma unroll
         for (int k = 0; k < NV; ++k) vi[k][0] = (R)v[3 * k], vi[k][1] = (R)v[3 * k + 1], vi[k][2] = (R)v[3 * k + 2];
-      } else {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) vi[k][0] = vi[k][1] = vi[k][2] = (R)0;
+        for (int k = 0; k < SL; ++k) vil[k][0] = v[3 * k], vil[k][1] = v[3 * k + 1], vil[k][2] = v[3 * k + 2];
       }
       double fx = 0.0, fy = 0.0, fz = 0.0, tx = 0.0, ty = 0.0, tz = 0.0, uu = 0.0, wx = 0.0, wy = 0.0, wz = 0.0;
       double ush = 0.0;  // LJTS shifts of the interacting molecule pairs (mixtures)
       int nn = 0;
+      int cnt = 0;
+      unsigned char *mylist = list + lane;
+      // pass 2 over the listed hits of the current window
+      auto flush = [&]() {
+        scnt[lane] = cnt;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (act) {
+          int H = 0;
+          for (int s2 = 0; s2 < NS; ++s2) H += scnt[il + s2 * hc];
+          const int q0 = H * sl / NS, q1 = H * (sl + 1) / NS;
+          int sp = 0, j = q0, csp = scnt[il];
+          for (int q = q0; q < q1; ++q, ++j) {
+            while (j >= csp) j -= csp, ++sp, csp = scnt[il + sp * hc];
+            const int u = list[il + sp * hc + 64 * j];
+            const double dx = xi - jp[3 * u], dy = yi - jp[3 * u + 1], dz = zi - jp[3 * u + 2];
+            PairAcc<R> acc{{0, 0, 0}, {0, 0, 0}, 0};
+            const int cj = MIX ? jc_[u] : 0;
+            mol_pair<SL, SC, SD, SQ, MIX, R>(md, ci, cj, vil, vi, jl[u], jv[u], dx, dy, dz, acc);
+            addto(fx, acc.F[0]), addto(fy, acc.F[1]), addto(fz, acc.F[2]);
+            addto(tx, acc.T[0]), addto(ty, acc.T[1]), addto(tz, acc.T[2]);
+            addto(uu, acc.u);
+            wx = fma(dx, (double)acc.F[0], wx);
+            wy = fma(dy, (double)acc.F[1], wy);
+            wz = fma(dz, (double)acc.F[2], wz);
+            if (MIX) ush += md->shift_sum[ci][cj];
+            nn += 1;
+          }
+        }
+        cnt = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      };
       for (int jc = 0; jc < M; jc += CAP) {
         const int mj = min(CAP, M - jc);
         __syncthreads();
-        for (int t = lane; t < mj; t += 64) {
+        for (int t = tid; t < mj; t += 64 * W) {
           const int g = jc + t;
           const int k = find_nb(nb.off, g);
           const int src = nb.start[k] + (g - nb.off[k]);
-          jx[t] = c.sx[src] + nb.sh[k][0];
-          jy[t] = c.sy[src] + nb.sh[k][1];
-          jz[t] = c.sz[src] + nb.sh[k][2];
+          jp[3 * t] = c.sx[src] + nb.sh[k][0];
+          jp[3 * t + 1] = c.sy[src] + nb.sh[k][1];
+          jp[3 * t + 2] = c.sz[src] + nb.sh[k][2];
           if (MIX) jc_[t] = c.scomp[src];  // written (clamped to [0, ncomp)) by the gather
           const double *v = c.svec + (int64_t)src * NV * 3;
 #pragma unroll
-          for (int q = 0; q < NV * 3; ++q) jv[t][q] = (R)v[q];
+          for (int q = 0; q < SL * 3; ++q) jl[t][q] = v[q];
+#pragma unroll
+          for (int q = SL * 3; q < NV * 3; ++q) jv[t][q - SL * 3] = (R)v[q];
         }
         __syncthreads();
-        if (act) {
-          const int self = self0 + iloc - jc;
-          for (int t = sl; t < mj; t += NS) {
-            const double dx = xi - jx[t], dy = yi - jy[t], dz = zi - jz[t];
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            if (r2 < rc2 && t != self) {
-              PairAcc<R> acc{{0, 0, 0}, {0, 0, 0}, 0};
-              const int cj = MIX ? jc_[t] : 0;
-              mol_pair<SL, SC, SD, SQ, MIX, R>(md, ci, cj, vi, jv[t], (R)dx, (R)dy, (R)dz, acc);
-              addto(fx, acc.F[0]), addto(fy, acc.F[1]), addto(fz, acc.F[2]);
-              addto(tx, acc.T[0]), addto(ty, acc.T[1]), addto(tz, acc.T[2]);
-              addto(uu, acc.u);
-              wx = fma(dx, (double)acc.F[0], wx);
-              wy = fma(dy, (double)acc.F[1], wy);
-              wz = fma(dz, (double)acc.F[2], wz);
-              if (MIX) ush += md->shift_sum[ci][cj];
-              nn += 1;
+        if (hc > 0) {
+          const int self = self0 + iloc - jc;  // window slot of the molecule itself (may be outside)
+          int kb = 0;
+          while (true) {
+            // pass 1: walk until the window ends or a list could overflow; the slot is always
+            // written, the count advances on a hit
+            for (; kb < mj && !__any(cnt > LCAP - 2); kb += 2 * NS) {
+              const int ta = kb + sla, tb = ta + NS;
+              const double ax = xi - jp[3 * ta], ay = yi - jp[3 * ta + 1], az = zi - jp[3 * ta + 2];
+              const double bx_ = xi - jp[3 * tb], by_ = yi - jp[3 * tb + 1], bz_ = zi - jp[3 * tb + 2];
+              const double ra = fma(az, az, fma(ay, ay, ax * ax));
+              const double rb = fma(bz_, bz_, fma(by_, by_, bx_ * bx_));
+              mylist[64 * cnt] = (unsigned char)ta;
+              cnt += (ta < mj && ra < rc2 && ta != self) ? 1 : 0;
+              mylist[64 * cnt] = (unsigned char)tb;
+              cnt += (tb < mj && rb < rc2 && tb != self) ? 1 : 0;
             }
+            flush();
+            if (kb >= mj) break;
           }
         }
       }
       uu -= MIX ? ush : (double)nn * md->shift_sum[0][0];
-#pragma unroll
-      for (int off = 16; off < 64; off <<= 1) {
-        if (off >= NI) {
-          fx += __shfl_xor(fx, off), fy += __shfl_xor(fy, off), fz += __shfl_xor(fz, off);
-          tx += __shfl_xor(tx, off), ty += __shfl_xor(ty, off), tz += __shfl_xor(tz, off);
-          uu += __shfl_xor(uu, off);
-          wx += __shfl_xor(wx, off), wy += __shfl_xor(wy, off), wz += __shfl_xor(wz, off);
-          nn += __shfl_xor(nn, off);
-        }
+      // slices of molecule il sit in lanes il + s hc: add them to lane il in slice order
+      double dn = (double)nn;
+      for (int s2 = 1; s2 < NS; ++s2) {
+        const int src = lane + s2 * hc;  // meaningful for lane < hc
+        const double f0 = __shfl(fx, src), f1 = __shfl(fy, src), f2 = __shfl(fz, src);
+        const double t0 = __shfl(tx, src), t1 = __shfl(ty, src), t2 = __shfl(tz, src);
+        const double u0 = __shfl(uu, src), w0 = __shfl(wx, src), w1 = __shfl(wy, src), w2 = __shfl(wz, src);
+        const double n0 = __shfl(dn, src);
+        if (lane < hc)
+          fx += f0, fy += f1, fz += f2, tx += t0, ty += t1, tz += t2, uu += u0, wx += w0, wy += w1, wz += w2,
+              dn += n0;
       }
-      if (sl == 0 && act) {
+      if (lane < hc) {
         const int orig = c.perm[hs + iloc];
         o.force[3 * orig] = fx, o.force[3 * orig + 1] = fy, o.force[3 * orig + 2] = fz;
         if (o.torque) o.torque[3 * orig] = tx, o.torque[3 * orig + 1] = ty, o.torque[3 * orig + 2] = tz;
         if (o.u_mol) o.u_mol[orig] = 0.5 * uu;
         if (o.w_mol) o.w_mol[orig] = 0.5 * (wx + wy + wz);
-        if (o.nnb_mol) o.nnb_mol[orig] = nn;
-        bu += 0.5 * uu, bwx += 0.5 * wx, bwy += 0.5 * wy, bwz += 0.5 * wz, bn += (double)nn;
+        if (o.nnb_mol) o.nnb_mol[orig] = (int)dn;
+        acc5[0] += 0.5 * uu, acc5[1] += 0.5 * wx, acc5[2] += 0.5 * wy, acc5[3] += 0.5 * wz, acc5[4] += dn;
       }
     }
   }
-  write_partial(o.partial, bu, bwx, bwy, bwz, bn);
+  write_partial_block<W>(o.partial, acc5, red);
 }
 
 // ---------------------------------------------------------------- deterministic reductions
@@ -699,9 +787,14 @@ __global__ void k_finish_forces(const double *s, double *uw, int64_t *npairs, do
   if (erow) erow[0] = U, erow[3] = W;
 }
 
-template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP>
-int launch_ms(const CellsDev &cd, const md_model *m, const PairOut &o, int64_t nb, hipStream_t s) {
-  k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, m->host.rc2, o);
+// Dense cells (mean occupancy >= 16) are shared by four wavefronts and staged in larger windows;
+// sparser ones take one wavefront each.
+template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP1, int CAP4>
+int launch_ms(const CellsDev &cd, const md_model *m, const PairOut &o, int64_t nb, double mean, hipStream_t s) {
+  if (mean >= 16.0)
+    k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP4, 4><<<(unsigned)nb, 256, 0, s>>>(cd, m->dev, m->host.rc2, o);
+  else
+    k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP1, 1><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, m->host.rc2, o);
   return check_hip(hipGetLastError(), "k_pair_ms");
 }
 
@@ -740,14 +833,15 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
     return check_hip(hipGetLastError(), "k_pair_lj1");
   }
   const Shape &S = m->shape;
+  const double mean = (double)c->N / (double)c->ncell;
   if (m->fixed_shape && S.lj == 2 && S.chg == 0 && S.dip == 0 && S.quad == 1)
-    return f32 ? launch_ms<float, 2, 0, 0, 1, false, 256>(cd, m, o, nb, s)
-               : launch_ms<double, 2, 0, 0, 1, false, 256>(cd, m, o, nb, s);
+    return f32 ? launch_ms<float, 2, 0, 0, 1, false, 128, 256>(cd, m, o, nb, mean, s)
+               : launch_ms<double, 2, 0, 0, 1, false, 128, 256>(cd, m, o, nb, mean, s);
   if (m->fixed_shape && S.lj == 3 && S.chg == 0 && S.dip == 1 && S.quad == 0)
-    return f32 ? launch_ms<float, 3, 0, 1, 0, false, 256>(cd, m, o, nb, s)
-               : launch_ms<double, 3, 0, 1, 0, false, 256>(cd, m, o, nb, s);
-  return f32 ? launch_ms<float, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64>(cd, m, o, nb, s)
-             : launch_ms<double, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64>(cd, m, o, nb, s);
+    return f32 ? launch_ms<float, 3, 0, 1, 0, false, 128, 256>(cd, m, o, nb, mean, s)
+               : launch_ms<double, 3, 0, 1, 0, false, 128, 256>(cd, m, o, nb, mean, s);
+  return f32 ? launch_ms<float, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64, 128>(cd, m, o, nb, mean, s)
+             : launch_ms<double, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64, 128>(cd, m, o, nb, mean, s);
 }
 
 int launch_reduce(md_model *m, int64_t nrows, int ncols, const double *rows, double *out, hipStream_t s) {

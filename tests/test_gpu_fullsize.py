@@ -71,7 +71,7 @@ def test_full_size_sampled_and_global(md, oracle, golden, name):
         np.testing.assert_allclose(r["fp64"]["uw"][2:5], gd["Wd"], rtol=1e-11)
         eU32 = abs(r["fp32"]["uw"][0] - gd["U"]) / abs(gd["U"])
         print(f"  fp32 vs golden: eps_U {eU32:.2e}", flush=True)
-        assert eU32 < (1e-9 if not multi else 1e-7)
+        assert eU32 < 1e-9
     else:
         print(f"  (no golden value for {name} yet)", flush=True)
 

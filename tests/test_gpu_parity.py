@@ -66,7 +66,8 @@ def test_cells_bit_exact(md, oracle, case):
     np.testing.assert_array_equal(v["perm"].cpu().numpy(), order)
 
 
-FORCE_CASES = ["c1_ljts_4000", "c3_small", "c4_small", "c5_small", "mixture_small", "gas_ragged", "one_cell"]
+FORCE_CASES = ["c1_ljts_4000", "c3_small", "c4_small", "c5_small", "mixture_small", "gas_ragged", "one_cell",
+               "c5_dilute", "mixture_dilute"]
 
 
 def _force_cfg(name):
@@ -79,6 +80,10 @@ def _force_cfg(name):
         g = np.stack(np.meshgrid(*[np.arange(6)] * 3, indexing="ij"), -1).reshape(-1, 3)[:200]
         c["pos"] = 0.2 + 0.45 * g + rng.uniform(-0.02, 0.02, size=(200, 3))
         return c
+    if name == "c5_dilute":  # about 11 molecules per cell: one wavefront per home cell
+        return W.random_gas(400, [14.0, 15.0, 16.5], W.four_site_model(), seed=17, T=1.2, dmin=1.0)
+    if name == "mixture_dilute":
+        return W.random_gas(400, [13.0, 15.0, 17.0], W.mixture_model(), seed=19, T=1.5, dmin=1.0)
     return W.make(name)
 
 
@@ -103,11 +108,11 @@ def test_forces_fp64_match_oracle(md, oracle, name):
     assert rel_rms(got["w_mol"], ref["w"]) < 1e-11
 
 
-# FP32: (force rel RMS, torque rel RMS, energy rel) bars per case.  LJ energies are evaluated in
-# FP64 from the FP32 reciprocal, so single-site fluids meet 1e-9 whatever the cancellation in U;
-# multi-site electrostatic energies stay FP32 (measured ~1e-9 (2CLJQ) .. 5e-8 (mixture)).
-FP32_BARS = {"c1_ljts_4000": (1e-5, None, 1e-9), "c3_small": (1e-5, None, 1e-9), "gas_ragged": (1e-5, None, 1e-9), "one_cell": (1e-5, None, 1e-9),
-             "c4_small": (1e-5, 1e-5, 1e-8), "c5_small": (1e-5, 1e-5, 1e-8), "mixture_small": (1e-5, 1e-5, 1e-7)}
+# FP32: (force rel RMS, torque rel RMS, energy rel) bars per case: the stated targets of the FP32
+# path (force 1e-5 relative RMS, energy 1e-9 relative).  Energies are summed in FP64 from FP64
+# parameters, LJ site separations are FP64, so the FP32 rounding left in U is random, not
+# systematic.
+FP32_BARS = {name: (1e-5, 1e-5, 1e-9) for name in FORCE_CASES}
 
 
 @pytest.mark.parametrize("name", FORCE_CASES)
@@ -122,7 +127,7 @@ def test_forces_fp32_within_stated_error(md, oracle, name):
     print(f"{name}: fp32 eps_F {eF:.2e} eps_U {eU:.2e}", flush=True)
     assert eF < fb
     assert eU < ub
-    if tb is not None:
+    if cfg["quat"] is not None:
         assert rel_rms(got["torque"], ref["T"]) < tb
 
 
