@@ -169,22 +169,33 @@ __device__ __forceinline__ void acc_zero(AdjAcc<SL, SC, SD, SQ> &acc) {
   acc.n = 0;
 }
 
+// Add the slices of molecule lane l (lanes l + s hc, s = 1 .. NS - 1) to lane l, in slice order.
 template <int SL, int SC, int SD, int SQ>
-__device__ __forceinline__ void acc_slice_sum(AdjAcc<SL, SC, SD, SQ> &acc, int off) {
+__device__ __forceinline__ void acc_gather(AdjAcc<SL, SC, SD, SQ> &acc, int hc, int NS) {
   using Acc = AdjAcc<SL, SC, SD, SQ>;
+  const int lane = threadIdx.x & 63;
+  const bool dst = lane < hc;
+  auto add = [&](double &v, int src) {
+    const double w = __shfl(v, src);
+    if (dst) v += w;
+  };
+  for (int s2 = 1; s2 < NS; ++s2) {
+    const int src = lane + s2 * hc;  // meaningful for lane < hc
 #pragma unroll
-  for (int a = 0; a < Acc::NSITE; ++a)
+    for (int a = 0; a < Acc::NSITE; ++a)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) acc.gs[a][k] += __shfl_xor(acc.gs[a][k], off);
+      for (int k = 0; k < 3; ++k) add(acc.gs[a][k], src);
 #pragma unroll
-  for (int a = 0; a < Acc::NAX; ++a)
+    for (int a = 0; a < Acc::NAX; ++a)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) acc.ga[a][k] += __shfl_xor(acc.ga[a][k], off);
+      for (int k = 0; k < 3; ++k) add(acc.ga[a][k], src);
 #pragma unroll
-  for (int a = 0; a < SL; ++a) acc.peps[a] += __shfl_xor(acc.peps[a], off), acc.psig[a] += __shfl_xor(acc.psig[a], off);
+    for (int a = 0; a < SL; ++a) add(acc.peps[a], src), add(acc.psig[a], src);
 #pragma unroll
-  for (int a = 0; a < Acc::NMOM; ++a) acc.pmom[a] += __shfl_xor(acc.pmom[a], off);
-  acc.n += __shfl_xor(acc.n, off);
+    for (int a = 0; a < Acc::NMOM; ++a) add(acc.pmom[a], src);
+    const int n = __shfl(acc.n, src);
+    if (dst) acc.n += n;
+  }
 }
 
 // Parameter-gradient slots of one molecule in a compile-time layout (per LJ site: eps, sigma,
@@ -194,63 +205,106 @@ template <int SL, int SC, int SD, int SQ> struct PSlots {
   static constexpr int chg = 5 * SL, dip = 5 * SL + 4 * SC, quad = 5 * SL + 4 * (SC + SD);
 };
 
-template <typename R, int SL, int SC, int SD, int SQ, bool MIX, bool SINGLE, int CAP>
-__global__ __launch_bounds__(64) void k_adjoint(CellsDev c, const ModelDev *__restrict__ md, const double *quat,
-                                                double rc2, AdjOut o) {
+// One block of W wavefronts per home cell, staged through shared LDS windows of CAP molecules as
+// in the force kernel; pass 1 lists the COM-cutoff hits, pass 2 recomputes each listed pair's
+// site terms into the lane's adjoint accumulators (the hits of a molecule split evenly over its
+// slice lanes), slices are then added in a fixed order.
+template <typename R, int SL, int SC, int SD, int SQ, bool MIX, bool SINGLE, int CAP, int W>
+__global__ __launch_bounds__(64 * W) void k_adjoint(CellsDev c, const ModelDev *__restrict__ md, const double *quat,
+                                                    double rc2, AdjOut o) {
   using S = Slots<SL, SC, SD, SQ>;
   using Acc = AdjAcc<SL, SC, SD, SQ>;
   using PS = PSlots<SL, SC, SD, SQ>;
   constexpr int NV = SINGLE ? 1 : S::nv;
-  __shared__ double jx[CAP], jy[CAP], jz[CAP];
+  constexpr int LCAP = 32;
+  constexpr int NB = MIX ? 256 : PS::np;
+  static_assert(CAP <= 256, "list entries are bytes");
+  __shared__ double jp[CAP * 3 + 48];  // slack: the walk reads up to 2 NS - 1 slots past the window
   __shared__ R jv[CAP][NV * 3];
   __shared__ int jc_[MIX ? CAP : 1];
+  __shared__ unsigned char lists[W][LCAP * 64];
+  __shared__ int scnts[W][64];
   __shared__ NbTable nb;
-  __shared__ double bsum[MIX ? 256 : PS::np];
-  const int lane = threadIdx.x;
+  __shared__ double bsums[W][NB];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  unsigned char *list = lists[wave];
+  int *scnt = scnts[wave];
+  double *bsum = bsums[wave];
   const int cell = xcd_remap(blockIdx.x, gridDim.x);
   const int hs = cell < c.ncell ? c.cell_start[cell] : 0;
-  const int hn = cell < c.ncell ? c.cell_start[cell + 1] - hs : 0;
+  const int hn = cell < c.ncell ? __builtin_amdgcn_readfirstlane(c.cell_start[cell + 1] - hs) : 0;
   const int ncol = md->nparam;
   if (o.pgrad)
     for (int k = lane; k < ncol; k += 64) bsum[k] = 0.0;
   if (hn > 0) {
-    build_nb(c, cell, nb);
+    if (tid < 64) build_nb(c, cell, nb);
     __syncthreads();
     const int M = nb.off[27];
     const int self0 = nb.off[13];
-    const int NI = hn <= 16 ? 16 : (hn <= 32 ? 32 : 64);
-    const int NS = 64 / NI;
-    const int il = lane & (NI - 1), sl = lane / NI;
-    for (int ic = 0; ic < hn; ic += 64) {
-      const int iloc = ic + il;
-      const bool act = iloc < hn;
-      double xi = 0.0, yi = 0.0, zi = 0.0;
+    for (int ic = 0; ic < hn; ic += 64 * W) {
+      // this round's molecules, split evenly over the wavefronts (wave-uniform)
+      const int rem = min(64 * W, hn - ic), base = rem / W, extra = rem % W;
+      const int hc = base + (wave < extra ? 1 : 0);
+      const int i0 = ic + wave * base + min(wave, extra);
+      const int NS = hc > 0 ? min(8, 64 / hc) : 1;
+      const int il = hc > 0 ? lane % hc : 0, sl = hc > 0 ? lane / hc : NS;
+      const bool act = sl < NS;
+      const int sla = act ? sl : 0;
+      const int iloc = i0 + il;
+      double xi = 1e30, yi = 1e30, zi = 1e30;  // idle lanes: no candidate is within the cutoff
       R vi[NV][3];
       int ci = 0;
 #pragma unroll
       for (int k = 0; k < NV; ++k) vi[k][0] = vi[k][1] = vi[k][2] = (R)0;
-      if (act) {
-        const int s = hs + iloc;
-        xi = c.sx[s], yi = c.sy[s], zi = c.sz[s];
-        if (MIX) ci = c.scomp[s];
+      {
+        const int sidx = hs + (hc > 0 ? iloc : 0);
+        if (act) xi = c.sx[sidx], yi = c.sy[sidx], zi = c.sz[sidx];
+        if (MIX) ci = c.scomp[sidx];
         if (!SINGLE) {
-          const double *v = c.svec + (int64_t)s * NV * 3;
+          const double *v = c.svec + (int64_t)sidx * NV * 3;
 #pragma unroll
           for (int k = 0; k < NV; ++k) vi[k][0] = (R)v[3 * k], vi[k][1] = (R)v[3 * k + 1], vi[k][2] = (R)v[3 * k + 2];
         }
       }
       Acc acc;
       acc_zero(acc);
+      int cnt = 0;
+      unsigned char *mylist = list + lane;
+      auto flush = [&]() {
+        scnt[lane] = cnt;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (act) {
+          int H = 0;
+          for (int s2 = 0; s2 < NS; ++s2) H += scnt[il + s2 * hc];
+          const int q0 = H * sl / NS, q1 = H * (sl + 1) / NS;
+          int sp = 0, j = q0, csp = scnt[il];
+          for (int q = q0; q < q1; ++q, ++j) {
+            while (j >= csp) j -= csp, ++sp, csp = scnt[il + sp * hc];
+            const int u = list[il + sp * hc + 64 * j];
+            const double dx = xi - jp[3 * u], dy = yi - jp[3 * u + 1], dz = zi - jp[3 * u + 2];
+            const int cj = MIX ? jc_[u] : 0;
+            adj_pair<SL, SC, SD, SQ, MIX, R>(md, ci, cj, vi, jv[u], (R)dx, (R)dy, (R)dz, acc);
+            acc.n += 1;
+          }
+        }
+        cnt = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      };
       for (int jc = 0; jc < M; jc += CAP) {
         const int mj = min(CAP, M - jc);
         __syncthreads();
-        for (int t = lane; t < mj; t += 64) {
+        for (int t = tid; t < mj; t += 64 * W) {
           const int g = jc + t;
           const int k = find_nb(nb.off, g);
           const int src = nb.start[k] + (g - nb.off[k]);
-          jx[t] = c.sx[src] + nb.sh[k][0];
-          jy[t] = c.sy[src] + nb.sh[k][1];
-          jz[t] = c.sz[src] + nb.sh[k][2];
+          jp[3 * t] = c.sx[src] + nb.sh[k][0];
+          jp[3 * t + 1] = c.sy[src] + nb.sh[k][1];
+          jp[3 * t + 2] = c.sz[src] + nb.sh[k][2];
           if (MIX) jc_[t] = c.scomp[src];
           if (!SINGLE) {
             const double *v = c.svec + (int64_t)src * NV * 3;
@@ -261,22 +315,28 @@ __global__ __launch_bounds__(64) void k_adjoint(CellsDev c, const ModelDev *__re
           }
         }
         __syncthreads();
-        if (act) {
-          const int self = self0 + iloc - jc;
-          for (int t = sl; t < mj; t += NS) {
-            const double dx = xi - jx[t], dy = yi - jy[t], dz = zi - jz[t];
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            if (r2 < rc2 && t != self) {
-              const int cj = MIX ? jc_[t] : 0;
-              adj_pair<SL, SC, SD, SQ, MIX, R>(md, ci, cj, vi, jv[t], (R)dx, (R)dy, (R)dz, acc);
-              acc.n += 1;
+        if (hc > 0) {
+          const int self = self0 + iloc - jc;  // window slot of the molecule itself (may be outside)
+          int kb = 0;
+          while (true) {
+            for (; kb < mj && !__any(cnt > LCAP - 2); kb += 2 * NS) {
+              const int ta = kb + sla, tb = ta + NS;
+              const double ax = xi - jp[3 * ta], ay = yi - jp[3 * ta + 1], az = zi - jp[3 * ta + 2];
+              const double bx_ = xi - jp[3 * tb], by_ = yi - jp[3 * tb + 1], bz_ = zi - jp[3 * tb + 2];
+              const double ra = fma(az, az, fma(ay, ay, ax * ax));
+              const double rb = fma(bz_, bz_, fma(by_, by_, bx_ * bx_));
+              mylist[64 * cnt] = (unsigned char)ta;
+              cnt += (ta < mj && ra < rc2 && ta != self) ? 1 : 0;
+              mylist[64 * cnt] = (unsigned char)tb;
+              cnt += (tb < mj && rb < rc2 && tb != self) ? 1 : 0;
             }
+            flush();
+            if (kb >= mj) break;
           }
         }
       }
-      for (int off = 16; off < 64; off <<= 1)
-        if (off >= NI) acc_slice_sum(acc, off);
-      const bool lead = act && sl == 0;
+      acc_gather(acc, hc, NS);
+      const bool lead = lane < hc;
       const CompDev &cd = md->comp[ci];
       double q[4] = {1.0, 0.0, 0.0, 0.0};
       int orig = 0;
@@ -375,13 +435,22 @@ __global__ __launch_bounds__(64) void k_adjoint(CellsDev c, const ModelDev *__re
   if (o.pgrad) {
     __syncthreads();
     double *row = o.pgrad + (int64_t)blockIdx.x * ncol;
-    for (int k = lane; k < ncol; k += 64) row[k] = bsum[k];
+    for (int k = tid; k < ncol; k += 64 * W) {
+      double v = bsums[0][k];
+      for (int w = 1; w < W; ++w) v += bsums[w][k];
+      row[k] = v;
+    }
   }
 }
 
+// Dense cells (mean occupancy >= 16) are shared by four wavefronts, sparser ones take one each.
 template <typename R, int SL, int SC, int SD, int SQ, bool MIX, bool SINGLE, int CAP>
-int launch_adj(const CellsDev &cd, const md_model *m, const double *quat, const AdjOut &o, int64_t nb, hipStream_t s) {
-  k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
+int launch_adj(const CellsDev &cd, const md_model *m, const double *quat, const AdjOut &o, int64_t nb, double mean,
+               hipStream_t s) {
+  if (mean >= 16.0)
+    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP, 4><<<(unsigned)nb, 256, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
+  else
+    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP, 1><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
   return check_hip(hipGetLastError(), "k_adjoint");
 }
 
@@ -396,17 +465,20 @@ int launch_adjoint(md_model *m, const md_cells *c, int precision, const AdjOut &
   *nblocks = nb;
   const bool f32 = precision == MD_FP32;
   const Shape &S = m->shape;
+  const double mean = (double)c->N / (double)c->ncell;
   if (m->single_site)
-    return f32 ? launch_adj<float, 1, 0, 0, 0, false, true, 512>(cd, m, nullptr, o, nb, s)
-               : launch_adj<double, 1, 0, 0, 0, false, true, 512>(cd, m, nullptr, o, nb, s);
+    return f32 ? launch_adj<float, 1, 0, 0, 0, false, true, 256>(cd, m, nullptr, o, nb, mean, s)
+               : launch_adj<double, 1, 0, 0, 0, false, true, 256>(cd, m, nullptr, o, nb, mean, s);
   if (m->fixed_shape && S.lj == 2 && S.chg == 0 && S.dip == 0 && S.quad == 1)
-    return f32 ? launch_adj<float, 2, 0, 0, 1, false, false, 256>(cd, m, quat, o, nb, s)
-               : launch_adj<double, 2, 0, 0, 1, false, false, 256>(cd, m, quat, o, nb, s);
+    return f32 ? launch_adj<float, 2, 0, 0, 1, false, false, 256>(cd, m, quat, o, nb, mean, s)
+               : launch_adj<double, 2, 0, 0, 1, false, false, 256>(cd, m, quat, o, nb, mean, s);
   if (m->fixed_shape && S.lj == 3 && S.chg == 0 && S.dip == 1 && S.quad == 0)
-    return f32 ? launch_adj<float, 3, 0, 1, 0, false, false, 256>(cd, m, quat, o, nb, s)
-               : launch_adj<double, 3, 0, 1, 0, false, false, 256>(cd, m, quat, o, nb, s);
-  return f32 ? launch_adj<float, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, false, 64>(cd, m, quat, o, nb, s)
-             : launch_adj<double, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, false, 64>(cd, m, quat, o, nb, s);
+    return f32 ? launch_adj<float, 3, 0, 1, 0, false, false, 256>(cd, m, quat, o, nb, mean, s)
+               : launch_adj<double, 3, 0, 1, 0, false, false, 256>(cd, m, quat, o, nb, mean, s);
+  return f32 ? launch_adj<float, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, false, 64>(cd, m, quat, o, nb,
+                                                                                                    mean, s)
+             : launch_adj<double, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, false, 64>(cd, m, quat, o, nb,
+                                                                                                     mean, s);
 }
 
 }  // namespace mdcell
