@@ -287,9 +287,9 @@ int md_cells_create(md_cells **out) {
 
 int md_cells_destroy(md_cells *c) {
   if (!c) return MD_OK;
-  dfree(c->cell_of), dfree(c->slot), dfree(c->tmp), dfree(c->perm), dfree(c->scomp);
+  dfree(c->cell_of), dfree(c->slot), dfree(c->tmp), dfree(c->perm), dfree(c->perm_prev), dfree(c->scomp);
   dfree(c->count), dfree(c->start), dfree(c->bsum);
-  dfree(c->sx), dfree(c->sy), dfree(c->sz), dfree(c->svec), dfree(c->xw);
+  dfree(c->sx), dfree(c->sy), dfree(c->sz), dfree(c->svec);
   delete c;
   return MD_OK;
 }
@@ -326,13 +326,16 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
   const int nvec = m->single_site ? 0 : m->shape.nvec();
   int rc;
   int64_t capN = c->cap_N, capC = c->cap_cell, capB = c->cap_blocks;
+  // a rebuild of the same N visits the molecules in the previous sorted order (fewer contended
+  // atomics, near-sequential writes); the result does not depend on the visiting order
+  const bool reuse_order = c->built && c->N == N && N <= capN;
   if (N > capN) {
     int64_t cap = 0;
     if ((rc = grow(c->cell_of, cap, N, "cell_of")) || (cap = 0, rc = grow(c->slot, cap, N, "slot")) ||
         (cap = 0, rc = grow(c->tmp, cap, N, "tmp")) || (cap = 0, rc = grow(c->perm, cap, N, "perm")) ||
+        (cap = 0, rc = grow(c->perm_prev, cap, N, "perm")) ||
         (cap = 0, rc = grow(c->scomp, cap, N, "scomp")) || (cap = 0, rc = grow(c->sx, cap, N, "sx")) ||
-        (cap = 0, rc = grow(c->sy, cap, N, "sy")) || (cap = 0, rc = grow(c->sz, cap, N, "sz")) ||
-        (cap = 0, rc = grow(c->xw, cap, N, "xw"))) {
+        (cap = 0, rc = grow(c->sy, cap, N, "sy")) || (cap = 0, rc = grow(c->sz, cap, N, "sz"))) {
       c->cap_N = 0;
       return rc;
     }
@@ -366,7 +369,12 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
   const double inv_h[3] = {(double)nc[0] / box[0], (double)nc[1] / box[1], (double)nc[2] / box[2]};
   hipEvent_t ev;
   prof_begin(m, PROF_BUILD, s, &ev);
-  rc = launch_build(m, c, pos, quat, m->host.ncomp > 1 ? comp : nullptr, N, inv_h, s);
+  const int32_t *order = nullptr;
+  if (reuse_order) {
+    std::swap(c->perm, c->perm_prev);
+    order = c->perm_prev;
+  }
+  rc = launch_build(m, c, pos, quat, m->host.ncomp > 1 ? comp : nullptr, N, inv_h, order, s);
   prof_end(m, PROF_BUILD, s, ev);
   if (rc) return rc;
   c->built = true;
@@ -377,7 +385,7 @@ static int forces_impl(md_model *m, const md_cells *c, int precision, double *fo
                        double *w_mol, int32_t *nnb_mol, double *uw, int64_t *npairs, double *erow, hipStream_t s) {
   const int64_t nb = pair_blocks(c->ncell);
   int rc;
-  if ((rc = grow(m->partial, m->cap_partial, std::max<int64_t>(nb * PARTIAL_COLS, 2 * ((c->N + 255) / 256)), "partial")))
+  if ((rc = grow(m->partial, m->cap_partial, std::max<int64_t>(nb * PARTIAL_COLS, 2 * ((3 * c->N + 255) / 256 + (c->N + 255) / 256)), "partial")))
     return rc;
   PairOut o{force, torque, u_mol, w_mol, nnb_mol, m->partial};
   int64_t nblocks = 0;
@@ -386,8 +394,7 @@ static int forces_impl(md_model *m, const md_cells *c, int precision, double *fo
   rc = launch_pair(m, c, precision, o, s, &nblocks);
   prof_end(m, PROF_PAIR, s, ev);
   if (rc) return rc;
-  if ((rc = launch_reduce(m, nblocks, PARTIAL_COLS, m->partial, m->uw, s))) return rc;
-  return launch_finish_forces(m->uw, uw, npairs, erow, s);
+  return launch_reduce_forces(m, nblocks, m->partial, uw, npairs, erow, s);
 }
 
 int md_forces(md_model *m, const md_cells *c, int precision, double *force, double *torque, double *u_mol,

@@ -18,19 +18,22 @@ __device__ __forceinline__ int bin1(double xw, double inv_h, int n) {
 
 struct BinArgs {
   const double *pos, *quat;
-  const int32_t *comp;
+  const int32_t *comp, *order;  // order: processing order (the previous build's permutation) or NULL
   int64_t N;
   double Lx, Ly, Lz, ihx, ihy, ihz;
   int32_t nx, ny, nz, ncomp, check_quat;
   int32_t *cell_of, *slot, *count, *status;
-  double *xw;
 };
 
-// Wrap + bin + per-cell histogram.  The returned atomic slot is only a provisional position;
-// the final order inside a cell is fixed by k_rank_gather.
+// Wrap + bin + per-cell histogram.  Thread d takes molecule order[d] (identity without an order):
+// with the previous build's permutation, neighbouring threads mostly fall into the same cell, and
+// each run of equal cells inside a wavefront takes one atomic add.  The slot it returns is only a
+// provisional position; the final order inside a cell is fixed by k_rank_gather.
 __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.N) return;
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool valid = d < a.N;
+  const int64_t i = valid ? (a.order ? (int64_t)a.order[d] : d) : 0;
   double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
   int flags = 0;
   if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
@@ -46,15 +49,26 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
     const double n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
     if (!(fabs(n2 - 1.0) <= 1e-6)) flags |= MD_DEV_QUAT;
   }
-  if (flags) atomicOr(a.status, flags);
-  const double xwr = wrap1(x, a.Lx);
-  a.xw[i] = xwr;
-  const int cx = bin1(xwr, a.ihx, a.nx);
+  if (flags && valid) atomicOr(a.status, flags);
+  const int cx = bin1(wrap1(x, a.Lx), a.ihx, a.nx);
   const int cy = bin1(wrap1(y, a.Ly), a.ihy, a.ny);
   const int cz = bin1(wrap1(z, a.Lz), a.ihz, a.nz);
-  const int cell = (cz * a.ny + cy) * a.nx + cx;
-  a.cell_of[i] = cell;
-  a.slot[i] = atomicAdd(a.count + cell, 1);
+  const int cell = valid ? (cz * a.ny + cy) * a.nx + cx : -1;
+  // runs of equal cells among consecutive lanes: the run head adds the run length
+  const int prev = __shfl_up(cell, 1, 64);
+  const bool head = lane == 0 || prev != cell;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1);
+  const int hl = 63 - __clzll(heads & upto);  // this lane's run head
+  const unsigned long long after = heads & ~upto;
+  const int next = after ? __ffsll(after) - 1 : 64;  // first head after this lane
+  int base = 0;
+  if (head && valid) base = atomicAdd(a.count + cell, next - lane);
+  base = __shfl(base, hl, 64);
+  if (valid) {
+    a.cell_of[i] = cell;
+    a.slot[i] = base + (lane - hl);
+  }
 }
 
 // ---------------------------------------------------------------- exclusive scan of counts
@@ -141,8 +155,8 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t *cell_of, const i
 }
 
 struct GatherArgs {
-  const double *pos, *quat, *xw;
-  const int32_t *comp, *cell_of, *start, *tmp;
+  const double *pos, *quat;
+  const int32_t *comp, *cell_of, *start, *tmp, *order;
   int64_t N;
   double Lx, Ly, Lz;
   const ModelDev *md;
@@ -158,22 +172,19 @@ __device__ __forceinline__ void rotate(const double q[4], const double v[3], dou
   o[2] = 2.0 * (x * z - w * y) * v[0] + 2.0 * (y * z + w * x) * v[1] + (w * w - x * x - y * y + z * z) * v[2];
 }
 
-// Final position of molecule i inside its cell = number of molecules of the same cell that come
-// before it in (wrapped x, original index) order; then gather the sorted copies.  Ordering a
-// cell by x makes every x-row of cells x-sorted, which the pair kernel uses to cut its partner
-// windows; ties in x fall back to the original index, so the order is deterministic.
+// Final position of molecule i inside its cell = number of molecules of the same cell with a
+// smaller original index (a stable counting sort whatever order the atomic slots came in); then
+// gather the sorted copies.  The cell's entries are contiguous in tmp, so the ranking reads
+// cached words only.  Thread d takes molecule order[d] (identity without an order): in the
+// previous build's order the sorted copies are written nearly in sequence.
 __global__ __launch_bounds__(256) void k_rank_gather(GatherArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.N) return;
+  const int64_t dd = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (dd >= a.N) return;
+  const int64_t i = a.order ? (int64_t)a.order[dd] : dd;
   const int c = a.cell_of[i];
   const int s = a.start[c], n = a.start[c + 1] - s;
-  const double xi = a.xw[i];
   int rank = 0;
-  for (int k = 0; k < n; ++k) {
-    const int32_t j = a.tmp[s + k];
-    const double xj = a.xw[j];
-    rank += (xj < xi || (xj == xi && j < (int32_t)i)) ? 1 : 0;
-  }
+  for (int k = 0; k < n; ++k) rank += a.tmp[s + k] < (int32_t)i ? 1 : 0;
   const int d = s + rank;
   a.perm[d] = (int32_t)i;
   double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
@@ -261,13 +272,13 @@ int launch_scale_copy(const double *src, double *dst, int64_t n, double a, hipSt
 }
 
 int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat, const int32_t *comp, int64_t N,
-                 const double inv_h[3], hipStream_t s) {
+                 const double inv_h[3], const int32_t *order, hipStream_t s) {
   int rc;
   if ((rc = launch_fill_i32(c->count, c->ncell, 0, s))) return rc;
-  BinArgs b{pos,      quat,      comp,      N,        c->box[0],       c->box[1],
+  BinArgs b{pos,      quat,      comp,      order,     N,        c->box[0],       c->box[1],
             c->box[2], inv_h[0], inv_h[1], inv_h[2], c->nc[0],        c->nc[1],
             c->nc[2], m->host.ncomp, (int32_t)((m->flags & MD_CHECK) != 0), c->cell_of, c->slot, c->count,
-            m->status, c->xw};
+            m->status};
   k_bin<<<nblk(N, 256), 256, 0, s>>>(b);
   if ((rc = check_hip(hipGetLastError(), "k_bin"))) return rc;
   const int64_t nb = (c->ncell + SCAN_TILE - 1) / SCAN_TILE;
@@ -277,7 +288,7 @@ int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat
   if ((rc = check_hip(hipGetLastError(), "k_scan"))) return rc;
   k_scatter<<<nblk(N, 256), 256, 0, s>>>(c->cell_of, c->slot, c->start, N, c->tmp);
   if ((rc = check_hip(hipGetLastError(), "k_scatter"))) return rc;
-  GatherArgs g{pos, m->single_site ? nullptr : quat, c->xw, comp, c->cell_of, c->start, c->tmp, N, c->box[0], c->box[1],
+  GatherArgs g{pos, m->single_site ? nullptr : quat, comp, c->cell_of, c->start, c->tmp, order, N, c->box[0], c->box[1],
                c->box[2], m->dev, m->shape.lj, m->shape.chg, m->shape.dip, m->shape.quad, c->nvec, c->perm,
                m->single_site ? nullptr : c->scomp, c->sx, c->sy, c->sz, m->single_site ? nullptr : c->svec};
   k_rank_gather<<<nblk(N, 256), 256, 0, s>>>(g);

@@ -92,8 +92,9 @@ struct md_cells {
   const md_model *model = nullptr;
   const double *quat = nullptr;  // caller's quaternion array of the last build (read by the adjoint)
   int32_t *cell_of = nullptr, *slot = nullptr, *tmp = nullptr, *perm = nullptr, *scomp = nullptr;
+  int32_t *perm_prev = nullptr;  // the other buffer of the permutation pair (previous build's order)
   int32_t *count = nullptr, *start = nullptr, *bsum = nullptr;
-  double *sx = nullptr, *sy = nullptr, *sz = nullptr, *svec = nullptr, *xw = nullptr;
+  double *sx = nullptr, *sy = nullptr, *sz = nullptr, *svec = nullptr;
 };
 
 struct md_model {
@@ -139,10 +140,11 @@ void prof_end(md_model *m, int group, hipStream_t s, hipEvent_t a);
 
 // launchers
 int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat, const int32_t *comp, int64_t N,
-                 const double inv_h[3], hipStream_t s);
+                 const double inv_h[3], const int32_t *order, hipStream_t s);
 int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o, hipStream_t s, int64_t *nblocks);
 int launch_reduce(md_model *m, int64_t nrows, int ncols, const double *rows, double *out, hipStream_t s);
-int launch_finish_forces(const double *sums, double *uw, int64_t *npairs, double *energies_row, hipStream_t s);
+int launch_reduce_forces(md_model *m, int64_t nrows, const double *rows, double *uw, int64_t *npairs,
+                         double *energies_row, hipStream_t s);
 int launch_leapfrog(md_model *m, double *pos, double *vel, double *quat, double *angmom, const int32_t *comp,
                     int64_t N, const double box[3], double dt, const double *force, const double *torque,
                     double *energies_row, hipStream_t s);

@@ -757,34 +757,56 @@ constexpr int RED_THREADS = 256;
 constexpr int RED_BLOCKS = 256;
 constexpr int RED_MAXCOLS = 256;
 
-// Stage 1: block b sums rows [b * chunk, (b + 1) * chunk) of a [nrows][ncols] table, thread t
-// taking rows t, t + 256, ... in order, then a fixed LDS tree.  Stage 2 (nblocks = 1) repeats
-// on the per-block results.  The summation order never depends on timing.
+// Column sums of a [nrows][ncols] table in two launches.  Stage 1: block b sums rows
+// [b chunk, (b + 1) chunk), thread t taking rows t, t + 256, ... in order, then a fixed LDS tree,
+// into red2[b].  Stage 2 (one block) sums red2 over b in the same way and writes the result, for
+// the force sums also U, W, W_aa, the pair count and the energies row.  The summation order never
+// depends on timing.
+__device__ __forceinline__ double block_tree(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_cols(const double *rows, int64_t nrows, int ncols,
                                                              int64_t chunk, double *out) {
   __shared__ double sh[RED_THREADS];
   const int64_t r0 = (int64_t)blockIdx.x * chunk;
   const int64_t r1 = min(nrows, r0 + chunk);
   for (int col = 0; col < ncols; ++col) {
-    double s = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += RED_THREADS) s += rows[r * ncols + col];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = RED_THREADS / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * ncols + col] = sh[0];
-    __syncthreads();
+    double v = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += RED_THREADS) v += rows[r * ncols + col];
+    v = block_tree(v, sh);
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * ncols + col] = v;
   }
 }
 
-__global__ void k_finish_forces(const double *s, double *uw, int64_t *npairs, double *erow) {
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double *red2, int nb, int ncols, double *out,
+                                                              int finish, double *uw, int64_t *npairs, double *erow) {
+  __shared__ double sh[RED_THREADS];
+  __shared__ double res[RED_MAXCOLS];
+  for (int col = 0; col < ncols; ++col) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += RED_THREADS) v += red2[(int64_t)b * ncols + col];
+    v = block_tree(v, sh);
+    if (threadIdx.x == 0) res[col] = v;
+  }
   if (threadIdx.x != 0) return;
-  const double U = s[0], W = s[1] + s[2] + s[3];
-  uw[0] = U, uw[1] = W, uw[2] = s[1], uw[3] = s[2], uw[4] = s[3];
-  if (npairs) *npairs = (int64_t)(s[4] * 0.5);
-  if (erow) erow[0] = U, erow[3] = W;
+  if (finish) {
+    const double U = res[0], W = res[1] + res[2] + res[3];
+    uw[0] = U, uw[1] = W, uw[2] = res[1], uw[3] = res[2], uw[4] = res[3];
+    if (npairs) *npairs = (int64_t)(res[4] * 0.5);
+    if (erow) erow[0] = U, erow[3] = W;
+  } else {
+    for (int col = 0; col < ncols; ++col) out[col] = res[col];
+  }
 }
 
 // Dense cells (mean occupancy >= 16) are shared by four wavefronts and staged in larger windows;
@@ -848,13 +870,16 @@ int launch_reduce(md_model *m, int64_t nrows, int ncols, const double *rows, dou
   if (ncols > RED_MAXCOLS) return set_error(MD_EINVAL, "reduction too wide");
   const int64_t chunk = (nrows + RED_BLOCKS - 1) / RED_BLOCKS;
   k_reduce_cols<<<RED_BLOCKS, RED_THREADS, 0, s>>>(rows, nrows, ncols, chunk > 0 ? chunk : 1, m->red2);
-  k_reduce_cols<<<1, RED_THREADS, 0, s>>>(m->red2, RED_BLOCKS, ncols, RED_BLOCKS, out);
-  return check_hip(hipGetLastError(), "k_reduce_cols");
+  k_reduce_final<<<1, RED_THREADS, 0, s>>>(m->red2, RED_BLOCKS, ncols, out, 0, nullptr, nullptr, nullptr);
+  return check_hip(hipGetLastError(), "k_reduce");
 }
 
-int launch_finish_forces(const double *sums, double *uw, int64_t *npairs, double *erow, hipStream_t s) {
-  k_finish_forces<<<1, 64, 0, s>>>(sums, uw, npairs, erow);
-  return check_hip(hipGetLastError(), "k_finish_forces");
+int launch_reduce_forces(md_model *m, int64_t nrows, const double *rows, double *uw, int64_t *npairs, double *erow,
+                         hipStream_t s) {
+  const int64_t chunk = (nrows + RED_BLOCKS - 1) / RED_BLOCKS;
+  k_reduce_cols<<<RED_BLOCKS, RED_THREADS, 0, s>>>(rows, nrows, PARTIAL_COLS, chunk > 0 ? chunk : 1, m->red2);
+  k_reduce_final<<<1, RED_THREADS, 0, s>>>(m->red2, RED_BLOCKS, PARTIAL_COLS, nullptr, 1, uw, npairs, erow);
+  return check_hip(hipGetLastError(), "k_reduce");
 }
 
 }  // namespace mdcell

@@ -1,6 +1,6 @@
 // Leapfrog integration (Sec. 3, Eqs. 2-5): translational kick-drift with periodic wrap and,
 // for molecules with inertia, Fincham's rotational leapfrog on quaternions with the space-frame
-// angular momentum.  One thread per molecule, HBM-bound (~120 B/molecule translational,
+// angular momentum.  HBM-bound (~120 B/molecule translational, one thread per Cartesian component;
 // ~+136 B rotational), with per-block kinetic-energy partials reduced deterministically.
 
 #include "md_internal.h"
@@ -15,7 +15,7 @@ struct LeapArgs {
   double Lx, Ly, Lz, dt;
   const double *force, *torque;
   const ModelDev *md;
-  double *partial;  // [gridDim.x][2]: K_trans, K_rot
+  double *partial;  // [rows][2]: K_trans, K_rot block partials
 };
 
 __device__ __forceinline__ void rotmat(const double *q, double A[3][3]) {
@@ -47,27 +47,52 @@ __device__ __forceinline__ void q_normalise(double *q) {
   q[0] /= n, q[1] /= n, q[2] /= n, q[3] /= n;
 }
 
-__global__ __launch_bounds__(256) void k_leapfrog(LeapArgs a) {
-  __shared__ double sk[2][4];
+// Fixed-order block sum of one value (wave shuffles, then the four wave sums in order) into
+// partial[row][col]; the other column of the row is set to zero.
+__device__ __forceinline__ void block_partial(double v, double *partial, int64_t row, int col) {
+  __shared__ double sk[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sk[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partial[2 * row + col] = ((sk[0] + sk[1]) + sk[2]) + sk[3];
+    partial[2 * row + 1 - col] = 0.0;
+  }
+}
+
+// Translational kick-drift, one thread per Cartesian component (3N threads, coalesced): v += dt F/m,
+// r = wrap(r + dt v); K_trans from the mid-step velocity.
+__global__ __launch_bounds__(256) void k_leapfrog_trans(LeapArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double kt = 0.0;
+  if (t < 3 * a.N) {
+    const int64_t i = t / 3;
+    const int k = (int)(t - 3 * i);
+    int c = a.comp ? a.comp[i] : 0;
+    if (c < 0 || c >= a.md->ncomp) c = 0;
+    const double mass = a.md->comp[c].mass;
+    const double vold = a.vel[t];
+    const double vnew = vold + a.dt * a.force[t] / mass;
+    const double vmid = 0.5 * (vold + vnew);
+    kt = 0.5 * mass * (vmid * vmid);
+    a.vel[t] = vnew;
+    a.pos[t] = wrap1(a.pos[t] + a.dt * vnew, k == 0 ? a.Lx : (k == 1 ? a.Ly : a.Lz));
+  }
+  block_partial(kt, a.partial, blockIdx.x, 0);
+}
+
+// Rotational leapfrog (Fincham), one thread per molecule; K_rot at the half step.  Block partials
+// go to rows row0 + blockIdx.x.
+__global__ __launch_bounds__(256) void k_leapfrog_rot(LeapArgs a, int64_t row0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double kt = 0.0, kr = 0.0;
+  double kr = 0.0;
   if (i < a.N) {
     int c = a.comp ? a.comp[i] : 0;
     if (c < 0 || c >= a.md->ncomp) c = 0;
     const CompDev &cd = a.md->comp[c];
-    const double L[3] = {a.Lx, a.Ly, a.Lz};
-    double kti = 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double vold = a.vel[3 * i + k];
-      const double vnew = vold + a.dt * a.force[3 * i + k] / cd.mass;
-      const double vmid = 0.5 * (vold + vnew);
-      kti += vmid * vmid;
-      a.vel[3 * i + k] = vnew;
-      a.pos[3 * i + k] = wrap1(a.pos[3 * i + k] + a.dt * vnew, L[k]);
-    }
-    kt = 0.5 * cd.mass * kti;
-    if (a.quat && a.angmom && cd.rotates) {
+    if (cd.rotates) {
       double q[4], jm[3], tq[3];
 #pragma unroll
       for (int k = 0; k < 4; ++k) q[k] = a.quat[4 * i + k];
@@ -92,17 +117,7 @@ __global__ __launch_bounds__(256) void k_leapfrog(LeapArgs a) {
       for (int k = 0; k < 3; ++k) a.angmom[3 * i + k] = jn[k];
     }
   }
-  // fixed-order block reduction: wave shuffles, then the four wave sums in order
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) kt += __shfl_xor(kt, o), kr += __shfl_xor(kr, o);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) sk[0][w] = kt, sk[1][w] = kr;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double* p = a.partial + 2 * (int64_t)blockIdx.x;
-    p[0] = ((sk[0][0] + sk[0][1]) + sk[0][2]) + sk[0][3];
-    p[1] = ((sk[1][0] + sk[1][1]) + sk[1][2]) + sk[1][3];
-  }
+  block_partial(kr, a.partial, row0 + blockIdx.x, 1);
 }
 
 }  // namespace
@@ -110,13 +125,16 @@ __global__ __launch_bounds__(256) void k_leapfrog(LeapArgs a) {
 int launch_leapfrog(md_model *m, double *pos, double *vel, double *quat, double *angmom, const int32_t *comp,
                     int64_t N, const double box[3], double dt, const double *force, const double *torque,
                     double *energies_row, hipStream_t s) {
-  const int64_t nb = (N + 255) / 256;
-  LeapArgs a{pos, vel, m->single_site ? nullptr : quat, m->single_site ? nullptr : angmom, comp, N, box[0], box[1],
+  const int64_t nt = (3 * N + 255) / 256;
+  const bool rot = !m->single_site && quat && angmom;
+  const int64_t nr = rot ? (N + 255) / 256 : 0;
+  LeapArgs a{pos, vel, rot ? quat : nullptr, rot ? angmom : nullptr, comp, N, box[0], box[1],
              box[2], dt, force, torque, m->dev, m->partial};
-  k_leapfrog<<<(unsigned)nb, 256, 0, s>>>(a);
+  k_leapfrog_trans<<<(unsigned)nt, 256, 0, s>>>(a);
+  if (rot) k_leapfrog_rot<<<(unsigned)nr, 256, 0, s>>>(a, nt);
   int rc = check_hip(hipGetLastError(), "k_leapfrog");
   if (rc) return rc;
-  if (energies_row) return launch_reduce(m, nb, 2, m->partial, energies_row + 1, s);
+  if (energies_row) return launch_reduce(m, nt + nr, 2, m->partial, energies_row + 1, s);
   return MD_OK;
 }
 

@@ -51,7 +51,7 @@ CELL_CASES = {
 def test_cells_bit_exact(md, oracle, case):
     cfg = CELL_CASES[case]()
     pos = cfg["pos"] * (3.0 if case == "outside_box" else 1.0) - (7.0 if case == "outside_box" else 0.0)
-    ref_cell, ref_w, ncell = oracle.bin_cells(pos, cfg["box"], cfg["model"]["rc"])
+    ref_cell, _, ncell = oracle.bin_cells(pos, cfg["box"], cfg["model"]["rc"])
     _, m, cells = run_forces(md, cfg, "fp64", pos=pos)
     v = cells.view()
     assert v["ncell"] == ncell and v["nc"] == oracle.ncells(cfg["box"], cfg["model"]["rc"])
@@ -61,9 +61,32 @@ def test_cells_bit_exact(md, oracle, case):
     start = v["cell_start"].cpu().numpy()
     np.testing.assert_array_equal(np.diff(start), counts)
     assert start[0] == 0 and start[-1] == len(ref_cell)
-    # sorted by cell, inside a cell by wrapped x, ties by original index
-    order = np.lexsort((np.arange(len(ref_cell)), ref_w[:, 0], ref_cell))
+    # stable sort by cell: inside a cell by original index
+    order = np.lexsort((np.arange(len(ref_cell)), ref_cell))
     np.testing.assert_array_equal(v["perm"].cpu().numpy(), order)
+
+
+def test_cells_rebuild_in_previous_order(md, oracle):
+    """A rebuild of the same cells object (same N) visits molecules in the previous sorted order;
+    the cells, the permutation and the forces must still equal those of a fresh build."""
+    cfg = W.make("c1_ljts_4000")
+    rng = W.rng_for(77)
+    moved = cfg["pos"] + rng.uniform(-0.6, 0.6, size=cfg["pos"].shape)  # many molecules change cell
+    m = md.Model(cfg["model"])
+    reused = md.Cells()
+    md.build_cells(m, reused, dev(cfg["pos"]), None, None, cfg["box"])
+    md.build_cells(m, reused, dev(moved), None, None, cfg["box"])
+    fresh = md.Cells()
+    md.build_cells(m, fresh, dev(moved), None, None, cfg["box"])
+    ref_cell, _, _ = oracle.bin_cells(moved, cfg["box"], cfg["model"]["rc"])
+    a, b = reused.view(), fresh.view()
+    np.testing.assert_array_equal(a["cell_of"].cpu().numpy(), ref_cell)
+    for k in ("cell_of", "cell_start", "perm"):
+        np.testing.assert_array_equal(a[k].cpu().numpy(), b[k].cpu().numpy())
+    np.testing.assert_array_equal(a["perm"].cpu().numpy(), np.lexsort((np.arange(len(ref_cell)), ref_cell)))
+    fa, fb = md.forces(m, reused, "fp64"), md.forces(m, fresh, "fp64")
+    for k in ("force", "uw", "nnb"):
+        np.testing.assert_array_equal(fa[k].cpu().numpy(), fb[k].cpu().numpy())
 
 
 FORCE_CASES = ["c1_ljts_4000", "c3_small", "c4_small", "c5_small", "mixture_small", "gas_ragged", "one_cell",
