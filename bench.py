@@ -220,6 +220,33 @@ def main():
         model.profile(False)
         return wall, ms / k / 1e3
 
+    # ---- cell build (wrap, bin, stable counting sort, sorted gather), HBM-bound ----
+    def time_builds(n):
+        for _ in range(2):
+            md.build_cells(model, cells, pos0, quat0, comp_t, cfg["box"])
+        torch.cuda.synchronize()
+        model.profile(True)
+        for _ in range(n):
+            md.build_cells(model, cells, pos0, quat0, comp_t, cfg["box"])
+        torch.cuda.synchronize()
+        ms, k = model.profile_read("build")
+        model.profile(False)
+        return ms / k / 1e3
+
+    build_s = time_builds(max(5, args.force_evals // 5))
+    ncell_total = int(np.prod(v["nc"]))
+    # algorithmic bytes: read the COM (24 B); write cell id (4 B), permutation (4 B) and the sorted
+    # FP64 COM copy (24 B) per molecule, the cell start table (4 B per cell); multi-site models add
+    # the quaternion (32 B) and component id (4 B) read and the component id (4 B) and world-frame
+    # site vectors (24 B each) written
+    build_bytes_mol = 56.0
+    if multi:
+        kinds = [[st["kind"] for st in c_["sites"]] for c_ in cfg["model"]["components"]]
+        nv = sum(max(k.count(kind) for k in kinds) * w for kind, w in
+                 (("lj", 1), ("charge", 1), ("dipole", 2), ("quadrupole", 2)))
+        build_bytes_mol += 40.0 + 24.0 * nv
+    build_bytes = build_bytes_mol * N + 4.0 * (ncell_total + 1)
+
     f32_wall, f32_pair = time_forces("fp32", args.force_evals)
     f64_wall, f64_pair = (None, None) if args.no_fp64 else time_forces("fp64", args.force_evals)
 
@@ -281,6 +308,11 @@ def main():
                      "algorithmic_flop_per_launch": W_alg,
                      "accounting": "8 FLOP per half-shell distance test (D) + 24 FLOP per unique interacting pair (P)",
                      "frac_of_nonpacked_fp32_issue": W_alg / f32_pair / (PEAK_FP32 / 2)},
+        "cell_sort_roofline": {"bound": "hbm", "achieved": build_bytes / build_s / 1e9, "peak": PEAK_HBM / 1e9,
+                               "unit": "GB/s", "frac": build_bytes / build_s / PEAK_HBM,
+                               "ms_per_build": 1e3 * build_s, "algorithmic_bytes_per_build": build_bytes,
+                               "accounting": f"{build_bytes_mol:.0f} B per molecule + 4 B per cell",
+                               "kernels": "k_fill_i32, k_bin, k_scan_local/top/add, k_scatter, k_rank_gather"},
     }
     if not args.no_fp64:
         out["fp64"] = {"interactions_per_s": P * args.steps / t64, "ms_per_step": 1e3 * t64 / args.steps,
