@@ -48,24 +48,27 @@ def distance_tests(counts3d):
     return float(nd.sum() - 0.5 * c.sum())
 
 
-def pair_traffic(kernel_sources):
-    """HBM bytes per pair-kernel launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source (hash recorded in the summary); else None."""
+def pair_counters(kernel_sources):
+    """(HBM bytes, executed FP operations) per pair-kernel launch from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source (hash recorded in the summary);
+    else (None, None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_pair_lj1_c2_lj_1m_counters.md")
     if not os.path.exists(path):
-        return None
+        return None, None
     h = hashlib.sha256()
     for f in kernel_sources:
         h.update(open(os.path.join(ROOT, "paper_1408_4599_amd", "csrc", f), "rb").read())
     text = open(path).read()
-    src, val = None, None
+    src, val, flop = None, None, None
     for line in text.splitlines():
         if line.startswith("source_sha256:"):
             src = line.split(":", 1)[1].strip()
         if line.startswith("traffic_bytes_per_launch:"):
             val = float(line.split(":", 1)[1].strip())
-    return val if (src == h.hexdigest() and val is not None) else None
+        if line.startswith("Executed floating-point operations per dispatch"):
+            flop = float(line.rsplit(":", 1)[1].strip())
+    return (val, flop) if src == h.hexdigest() else (None, None)
 
 
 def measure_extra(md, W, torch, name, evals, steps, adjoint=False):
@@ -278,6 +281,7 @@ def main():
     value = P * args.steps / t32
     E = e32[:, 0] + e32[:, 1] + e32[:, 2]
     W_alg = 8.0 * D + 24.0 * P
+    traffic, executed = pair_counters(["md_pair.hip", "md_device.h", "md_internal.h"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -303,11 +307,13 @@ def main():
         "nve_rel_energy_spread_fp32": float(np.abs(E - E[0]).max() / abs(E[0])),
         "roofline": {"bound": "alu", "achieved": W_alg / f32_pair / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": W_alg / f32_pair / PEAK_FP32,
-                     "traffic": pair_traffic(["md_pair.hip", "md_device.h", "md_internal.h"]),
+                     "traffic": traffic,
                      "kernel": "k_pair_lj1<float>" if model.single_site else "k_pair_ms<float>",
                      "algorithmic_flop_per_launch": W_alg,
                      "accounting": "8 FLOP per half-shell distance test (D) + 24 FLOP per unique interacting pair (P)",
-                     "frac_of_nonpacked_fp32_issue": W_alg / f32_pair / (PEAK_FP32 / 2)},
+                     "frac_of_nonpacked_fp32_issue": W_alg / f32_pair / (PEAK_FP32 / 2),
+                     "executed_flop_per_launch": executed,
+                     "executed_frac": None if executed is None else executed / f32_pair / PEAK_FP32},
         "cell_sort_roofline": {"bound": "hbm", "achieved": build_bytes / build_s / 1e9, "peak": PEAK_HBM / 1e9,
                                "unit": "GB/s", "frac": build_bytes / build_s / PEAK_HBM,
                                "ms_per_build": 1e3 * build_s, "algorithmic_bytes_per_build": build_bytes,

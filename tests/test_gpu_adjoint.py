@@ -37,6 +37,8 @@ def _abi_params(model, pg):
 
 
 def _cfg(name):
+    if name == "c5_dilute":  # about 11 molecules per cell: one wavefront per home cell
+        return W.random_gas(400, [14.0, 15.0, 16.5], W.four_site_model(), seed=17, T=1.2, dmin=1.0)
     if name == "c1_sub":
         c = W.make("c1_ljts_4000")
         c["pos"], c["vel"], c["comp"] = c["pos"][:1200], c["vel"][:1200], c["comp"][:1200]
@@ -48,7 +50,7 @@ def _cfg(name):
 def refs():
     from oracle import oracle_torch as OT
     out = {}
-    for name in ("c1_sub", "c4_small", "c5_small", "mixture_small"):
+    for name in ("c1_sub", "c4_small", "c5_small", "mixture_small", "c5_dilute"):
         c = _cfg(name)
         out[name] = (c, OT.gradients(c["model"], c["pos"], c["quat"], c["comp"], c["box"]))
     return out
@@ -58,7 +60,7 @@ BARS = {"fp64": (1e-10, 1e-10, 1e-10), "fp32": (1e-5, 1e-5, 1e-5)}
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["c1_sub", "c4_small", "c5_small", "mixture_small"])
+@pytest.mark.parametrize("name", ["c1_sub", "c4_small", "c5_small", "mixture_small", "c5_dilute"])
 def test_adjoint_matches_autograd_reference(md, refs, name, prec):
     c, ref = refs[name]
     m = md.Model(c["model"])

@@ -93,6 +93,20 @@ FORCE_CASES = ["c1_ljts_4000", "c3_small", "c4_small", "c5_small", "mixture_smal
                "c5_dilute", "mixture_dilute"]
 
 
+def _ms_cluster(n_cluster, n_background, seed):
+    """n_cluster 4-site molecules on a 0.45-spaced grid inside one cell of a 3 x 3 x 3-cell box
+    (overlapping sites, huge but finite energies) plus n_background molecules in the other cells:
+    a home cell larger than one round of the multi-site kernel."""
+    rng = W.rng_for(seed)
+    L = 12.5
+    c = W.random_gas(n_cluster + n_background, [L, L, L], W.four_site_model(), seed=seed, T=1.2)
+    g = np.stack(np.meshgrid(*[np.arange(9)] * 3, indexing="ij"), -1).reshape(-1, 3)[:n_cluster]
+    cluster = 0.2 + 0.45 * g + rng.uniform(-0.02, 0.02, size=g.shape)
+    back = rng.uniform(0.0, 1.0, size=(n_background, 3)) * np.array([L - 4.2, L, L]) + np.array([4.2, 0.0, 0.0])
+    c["pos"] = np.concatenate([cluster, back])
+    return c
+
+
 def _force_cfg(name):
     if name == "gas_ragged":
         return W.random_gas(1000, [9.1, 11.7, 14.2], W.lj_model(2.5), seed=7, dmin=0.75)
@@ -103,6 +117,10 @@ def _force_cfg(name):
         g = np.stack(np.meshgrid(*[np.arange(6)] * 3, indexing="ij"), -1).reshape(-1, 3)[:200]
         c["pos"] = 0.2 + 0.45 * g + rng.uniform(-0.02, 0.02, size=(200, 3))
         return c
+    if name == "ms_cluster_w1":  # 150 molecules in one cell, ~9 per cell overall: rounds of 64
+        return _ms_cluster(150, 100, 23)
+    if name == "ms_cluster_w4":  # 300 in one cell, ~17 per cell overall: four wavefronts, rounds of 256
+        return _ms_cluster(300, 160, 29)
     if name == "c5_dilute":  # about 11 molecules per cell: one wavefront per home cell
         return W.random_gas(400, [14.0, 15.0, 16.5], W.four_site_model(), seed=17, T=1.2, dmin=1.0)
     if name == "mixture_dilute":
@@ -110,7 +128,7 @@ def _force_cfg(name):
     return W.make(name)
 
 
-@pytest.mark.parametrize("name", FORCE_CASES)
+@pytest.mark.parametrize("name", FORCE_CASES + ["ms_cluster_w1", "ms_cluster_w4"])
 def test_forces_fp64_match_oracle(md, oracle, name):
     cfg = _force_cfg(name)
     ref = oracle.rows(cfg["model"], cfg["pos"], cfg["quat"], cfg["comp"], cfg["box"])
