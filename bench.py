@@ -327,6 +327,17 @@ def main():
                        "roofline_frac_fp64_peak": W_alg / f64_pair / PEAK_FP64}
         out["fp32_speedup_over_fp64"] = {"step": t64 / t32, "pair_kernel": f64_pair / f32_pair}
 
+    # the paper's own figures (CPU runs of single-site LJ / LJTS, Sec. 5): context, not a target
+    out["paper_context"] = {
+        "this_run_molecule_steps_per_s": N * args.steps / t32,
+        "paper_sequential": {"molecule_steps_per_s": 102400 * 1000 / 530.9,
+                             "hardware": "1 core, AMD Opteron 6276 @ 2.3 GHz",
+                             "workload": "LJTS planar interface, N = 102 400, r_c = 2.5, 1000 steps in 530.9 s"},
+        "paper_full_machine": {"molecule_steps_per_s": 4.125e12 / 40.0,
+                               "hardware": "SuperMUC, 147 456 Sandy Bridge cores, FP32 AVX128",
+                               "workload": "single-site LJ, 4.125e12 molecules, r_c = 3.5, about 40 s per step"},
+    }
+
     if not args.no_extra:
         extra = {}
         for name, ev, st, adj in (("c3_lj_slab_2m", 20, 20, False), ("c4_2cljq_500k", 10, 10, False),
@@ -350,8 +361,16 @@ def main():
             "force_rel_rms": float(np.linalg.norm(F32s - ref["F"]) / np.linalg.norm(ref["F"])),
             "fp64_force_rel_rms": float(np.linalg.norm(F64.cpu().numpy()[idx] - ref["F"]) / np.linalg.norm(ref["F"]))}
         t_full = tcpu * N / len(idx)
+        cpu_model = None
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
         out["cpu_baseline"] = {"value": P / t_full, "unit": "interactions/s", "cores": O.num_threads(),
-                               "kind": "oracle",
+                               "cpu_model": cpu_model, "kind": "oracle",
                                "sample": f"{len(idx)} of {N} molecules: full O(N) rows of the FP64 brute-force "
                                          f"oracle in {tcpu:.1f}s; rate scaled to all N rows (each pair visited "
                                          f"from both ends)"}
