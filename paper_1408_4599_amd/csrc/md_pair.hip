@@ -535,6 +535,7 @@ __device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci
   for (int a = 0; a < SL; ++a) {
     if (a >= nla) break;
     const double ax = dxd + vil[a][0], ay = dyd + vil[a][1], az = dzd + vil[a][2];
+    R fa[3] = {(R)0, (R)0, (R)0};  // force on site a from all LJ sites of j (one lever-arm product)
 #pragma unroll
     for (int b = 0; b < SL; ++b) {
       if (b >= nlb) break;
@@ -553,10 +554,10 @@ __device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci
       const double s2d = p.sig2 * ir2d;
       const double s6d = s2d * s2d * s2d;
       acc.u = fma(p.eps4 * s6d, s6d - 1.0, acc.u);
-      const R f[3] = {fs * (R)rx, fs * (R)ry, fs * (R)rz};
-      acc.F[0] += f[0], acc.F[1] += f[1], acc.F[2] += f[2];
-      cross_acc(acc.T, vi[a], f);
+      fa[0] += fs * (R)rx, fa[1] += fs * (R)ry, fa[2] += fs * (R)rz;
     }
+    acc.F[0] += fa[0], acc.F[1] += fa[1], acc.F[2] += fa[2];
+    cross_acc(acc.T, vi[a], fa);
   }
   const R dx = (R)dxd, dy = (R)dyd, dz = (R)dzd;
   const R *vj = vje;
