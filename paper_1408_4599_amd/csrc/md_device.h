@@ -131,36 +131,47 @@ __device__ __forceinline__ int find_nb(const int *off, int g) {
 // with respect to r and the cosines c_i = e_a.rhat, c_j = e_b.rhat, c_ij = e_a.e_b (rhat points
 // from site b of molecule j to site a of molecule i).  ir = 1/r; krc3 = kappa / r_c^3.
 // Per unit moment product: energy t (t0: the same without the reaction-field term) and its
-// partial derivatives with respect to r, c_i, c_j and c_ij.
+// partial derivatives with respect to r, c_i, c_j and c_ij; ang is t0 / r^-n, the angular factor
+// of the energy, with n = unit_rpow<KA, KB>().
 template <typename R> struct Unit {
-  R t, tr, ti, tj, tij, t0;
+  R t, tr, ti, tj, tij, t0, ang;
 };
+
+template <int KA, int KB> constexpr int unit_rpow() {
+  return 1 + (KA == KIND_CHG ? 0 : (KA == KIND_DIP ? 1 : 2)) + (KB == KIND_CHG ? 0 : (KB == KIND_DIP ? 1 : 2));
+}
 
 template <int KA, int KB, typename R>
 __device__ __forceinline__ Unit<R> unit_terms(R ir, R ci, R cj, R cij, R krc3) {
-  Unit<R> u{0, 0, 0, 0, 0, 0};
+  Unit<R> u{0, 0, 0, 0, 0, 0, 0};
   const R ir2 = ir * ir, ir3 = ir2 * ir, ir4 = ir3 * ir;
   if constexpr (KA == KIND_CHG && KB == KIND_CHG) {
+    u.ang = (R)1;
     u.t = ir;
     u.tr = -ir2;
   } else if constexpr (KA == KIND_CHG && KB == KIND_DIP) {
+    u.ang = cj;
     u.t = cj * ir2;
     u.tr = (R)-2 * cj * ir3;
     u.tj = ir2;
   } else if constexpr (KA == KIND_DIP && KB == KIND_CHG) {
+    u.ang = -ci;
     u.t = -ci * ir2;
     u.tr = (R)2 * ci * ir3;
     u.ti = -ir2;
   } else if constexpr (KA == KIND_CHG && KB == KIND_QUAD) {
-    u.t = (R)0.5 * fma((R)3 * cj, cj, (R)-1) * ir3;
+    u.ang = (R)0.5 * fma((R)3 * cj, cj, (R)-1);
+    u.t = u.ang * ir3;
     u.tr = (R)-3 * u.t * ir;
     u.tj = (R)3 * cj * ir3;
   } else if constexpr (KA == KIND_QUAD && KB == KIND_CHG) {
-    u.t = (R)0.5 * fma((R)3 * ci, ci, (R)-1) * ir3;
+    u.ang = (R)0.5 * fma((R)3 * ci, ci, (R)-1);
+    u.t = u.ang * ir3;
     u.tr = (R)-3 * u.t * ir;
     u.ti = (R)3 * ci * ir3;
   } else if constexpr (KA == KIND_DIP && KB == KIND_DIP) {
     const R g = fma((R)-3 * ci, cj, cij);
+    u.ang = g;
     u.t0 = g * ir3;
     u.t = fma(g, ir3, -krc3 * cij);
     u.tr = (R)-3 * g * ir4;
@@ -170,6 +181,7 @@ __device__ __forceinline__ Unit<R> unit_terms(R ir, R ci, R cj, R cij, R krc3) {
   } else if constexpr (KA == KIND_DIP && KB == KIND_QUAD) {
     const R p = (R)1.5 * ir4;
     const R g = ci - (R)5 * ci * cj * cj + (R)2 * cj * cij;
+    u.ang = (R)1.5 * g;
     u.t = p * g;
     u.tr = (R)-4 * u.t * ir;
     u.ti = p * fma((R)-5 * cj, cj, (R)1);
@@ -178,6 +190,7 @@ __device__ __forceinline__ Unit<R> unit_terms(R ir, R ci, R cj, R cij, R krc3) {
   } else if constexpr (KA == KIND_QUAD && KB == KIND_DIP) {
     const R p = (R)-1.5 * ir4;
     const R g = cj - (R)5 * cj * ci * ci + (R)2 * ci * cij;
+    u.ang = (R)-1.5 * g;
     u.t = p * g;
     u.tr = (R)-4 * u.t * ir;
     u.tj = p * fma((R)-5 * ci, ci, (R)1);
@@ -187,6 +200,7 @@ __device__ __forceinline__ Unit<R> unit_terms(R ir, R ci, R cj, R cij, R krc3) {
     const R p = (R)0.75 * ir4 * ir;
     const R s = fma((R)-5 * ci, cj, cij);
     const R ci2 = ci * ci, cj2 = cj * cj;
+    u.ang = (R)0.75 * ((R)1 - (R)5 * ci2 - (R)5 * cj2 - (R)15 * ci2 * cj2 + (R)2 * s * s);
     u.t = p * ((R)1 - (R)5 * ci2 - (R)5 * cj2 - (R)15 * ci2 * cj2 + (R)2 * s * s);
     u.tr = (R)-5 * u.t * ir;
     u.ti = p * ((R)-10 * ci - (R)30 * ci * cj2 - (R)20 * cj * s);

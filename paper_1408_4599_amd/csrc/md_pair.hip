@@ -456,7 +456,8 @@ template <typename R> struct PairAcc {
 // One electrostatic site pair: site a of i (offset oa, axis ea) and site b of j (ob, eb).
 template <int KA, int KB, typename R>
 __device__ __forceinline__ void elec_site(R pm, double pmd, const R *oa, const R *ea, const R *ob, const R *eb, R dx,
-                                          R dy, R dz, R krc3, double krc3d, PairAcc<R> &acc) {
+                                          R dy, R dz, double dxd, double dyd, double dzd, R krc3, double krc3d,
+                                          PairAcc<R> &acc) {
   const R rx = dx + oa[0] - ob[0], ry = dy + oa[1] - ob[1], rz = dz + oa[2] - ob[2];
   const R r2 = fma(rz, rz, fma(ry, ry, rx * rx));
   const R ir = rsq_nr<R>(r2);
@@ -485,7 +486,22 @@ __device__ __forceinline__ void elec_site(R pm, double pmd, const R *oa, const R
     }
     cross_acc(acc.T, ea, ga);  // tau -= e_a x dU/de_a
   }
-  double ue = (double)t.t0;
+  // energy in FP64: the site separation from the FP64 COM separation (exact when both sites sit
+  // at their centres), 1/r refined by one FP64 Newton step, times the angular factor
+  double ue;
+  if constexpr (sizeof(R) == 8) {
+    ue = t.t0;
+  } else {
+    const double rxd = dxd + (double)(oa[0] - ob[0]), ryd = dyd + (double)(oa[1] - ob[1]);
+    const double rzd = dzd + (double)(oa[2] - ob[2]);
+    const double r2d = fma(rzd, rzd, fma(ryd, ryd, rxd * rxd));
+    double y = (double)ir;
+    y = y * fma(-0.5 * r2d, y * y, 1.5);
+    double yn = y;
+#pragma unroll
+    for (int k = 1; k < unit_rpow<KA, KB>(); ++k) yn *= y;
+    ue = (double)t.ang * yn;
+  }
   if constexpr (KA == KIND_DIP && KB == KIND_DIP) ue = fma(-krc3d, (double)cij, ue);
   acc.u = fma(pmd, ue, acc.u);
 }
@@ -494,7 +510,8 @@ __device__ __forceinline__ void elec_site(R pm, double pmd, const R *oa, const R
 // vi: all site vectors of i; vj: the electrostatic site vectors of j (slots from SL on).
 template <int KA, int KB, int SL, int SC, int SD, int SQ, bool MIX, typename R>
 __device__ __forceinline__ void elec_group(const CompDev &A, const CompDev &B, const R (*vi)[3], const R *vj,
-                                           R dx, R dy, R dz, R krc3, double krc3d, PairAcc<R> &acc) {
+                                           R dx, R dy, R dz, double dxd, double dyd, double dzd, R krc3,
+                                           double krc3d, PairAcc<R> &acc) {
   using S = Slots<SL, SC, SD, SQ>;
   constexpr int NA = KA == KIND_CHG ? SC : (KA == KIND_DIP ? SD : SQ);
   constexpr int NB = KB == KIND_CHG ? SC : (KB == KIND_DIP ? SD : SQ);
@@ -514,7 +531,7 @@ __device__ __forceinline__ void elec_group(const CompDev &A, const CompDev &B, c
       if (b >= nb) break;
       const double mbd = KB == KIND_CHG ? B.chg_q[b] : (KB == KIND_DIP ? B.dip_mu[b] : B.quad_Q[b]);
       elec_site<KA, KB, R>(ma * (R)mbd, mad * mbd, vi[OA + a], vi[EA + a], vj + 3 * (OB - SL + b),
-                           vj + 3 * (EB - SL + b), dx, dy, dz, krc3, krc3d, acc);
+                           vj + 3 * (EB - SL + b), dx, dy, dz, dxd, dyd, dzd, krc3, krc3d, acc);
     }
   }
 }
@@ -565,25 +582,25 @@ __device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci
     const double krc3d = md->kappa_rc3;
     const R krc3 = (R)krc3d;
     if constexpr (SC > 0) {
-      elec_group<KIND_CHG, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
+      elec_group<KIND_CHG, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, dxd, dyd, dzd, krc3, krc3d, acc);
       if constexpr (SD > 0) {
-        elec_group<KIND_CHG, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
-        elec_group<KIND_DIP, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
+        elec_group<KIND_CHG, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, dxd, dyd, dzd, krc3, krc3d, acc);
+        elec_group<KIND_DIP, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, dxd, dyd, dzd, krc3, krc3d, acc);
       }
       if constexpr (SQ > 0) {
-        elec_group<KIND_CHG, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
-        elec_group<KIND_QUAD, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
+        elec_group<KIND_CHG, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, dxd, dyd, dzd, krc3, krc3d, acc);
+        elec_group<KIND_QUAD, KIND_CHG, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, dxd, dyd, dzd, krc3, krc3d, acc);
       }
     }
     if constexpr (SD > 0) {
-      elec_group<KIND_DIP, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
+      elec_group<KIND_DIP, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, dxd, dyd, dzd, krc3, krc3d, acc);
       if constexpr (SQ > 0) {
-        elec_group<KIND_DIP, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
-        elec_group<KIND_QUAD, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
+        elec_group<KIND_DIP, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, dxd, dyd, dzd, krc3, krc3d, acc);
+        elec_group<KIND_QUAD, KIND_DIP, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, dxd, dyd, dzd, krc3, krc3d, acc);
       }
     }
     if constexpr (SQ > 0)
-      elec_group<KIND_QUAD, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, krc3, krc3d, acc);
+      elec_group<KIND_QUAD, KIND_QUAD, SL, SC, SD, SQ, MIX>(A, B, vi, vj, dx, dy, dz, dxd, dyd, dzd, krc3, krc3d, acc);
   }
 }
 

@@ -92,6 +92,32 @@ def mixture_model(rc=3.5, eps_rf=20.0, shift=True):
             "rc": float(rc), "eps_rf": float(eps_rf), "lj_shift": bool(shift)}
 
 
+def mixture4_model(rc=3.5, eps_rf=20.0, shift=True):
+    """Four components (the most a model may hold): the two of mixture_model, a linear two-centre
+    LJ + quadrupole molecule (one principal moment zero) and a plain LJ atom (no rotation);
+    binary parameters xi, eta differ from 1."""
+    m = mixture_model(rc, eps_rf, shift)
+    c = {"sites": [{"kind": "lj", "pos": [0.0, 0.0, -0.25], "eps": 0.9, "sigma": 1.0},
+                   {"kind": "lj", "pos": [0.0, 0.0, 0.25], "eps": 0.9, "sigma": 1.0},
+                   {"kind": "quadrupole", "pos": [0.0, 0.0, 0.0], "dir": [0.0, 0.0, 1.0], "Q": 1.1}],
+         "mass": 1.0, "inertia": [0.0625, 0.0625, 0.0]}
+    d = {"sites": [{"kind": "lj", "pos": [0.0, 0.0, 0.0], "eps": 0.7, "sigma": 1.1}],
+         "mass": 0.8, "inertia": [0.0, 0.0, 0.0]}
+    xi = [[1.0, 0.95, 0.9, 1.05], [0.95, 1.0, 0.97, 1.0], [0.9, 0.97, 1.0, 0.93], [1.05, 1.0, 0.93, 1.0]]
+    eta = [[1.0, 1.02, 0.98, 1.0], [1.02, 1.0, 1.01, 0.99], [0.98, 1.01, 1.0, 1.03], [1.0, 0.99, 1.03, 1.0]]
+    m["components"] = m["components"] + [c, d]
+    m["xi"], m["eta"] = xi, eta
+    return m
+
+
+def mixture4_small(N=600, seed=27):
+    """The four-component mixture as a dilute random gas (minimum COM separation 1), components
+    drawn uniformly."""
+    c = random_gas(N, [14.0, 15.0, 16.0], mixture4_model(), seed=seed, T=1.5, name="mixture4_small", dmin=1.0)
+    c["comp"] = rng_for(seed + 1).integers(0, 4, size=N).astype(np.int32)
+    return c
+
+
 # ----------------------------------------------------------------------------- building blocks
 
 def rng_for(k: int) -> np.random.Generator:
@@ -341,6 +367,7 @@ CONFIGS = {
     "c5_small": c5_small,
     "c3_small": c3_small,
     "mixture_small": mixture_small,
+    "mixture4_small": mixture4_small,
 }
 
 

@@ -50,7 +50,7 @@ def _cfg(name):
 def refs():
     from oracle import oracle_torch as OT
     out = {}
-    for name in ("c1_sub", "c4_small", "c5_small", "mixture_small", "c5_dilute"):
+    for name in ("c1_sub", "c4_small", "c5_small", "mixture_small", "c5_dilute", "mixture4_small"):
         c = _cfg(name)
         out[name] = (c, OT.gradients(c["model"], c["pos"], c["quat"], c["comp"], c["box"]))
     return out
@@ -60,7 +60,7 @@ BARS = {"fp64": (1e-10, 1e-10, 1e-10), "fp32": (1e-5, 1e-5, 1e-5)}
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["c1_sub", "c4_small", "c5_small", "mixture_small", "c5_dilute"])
+@pytest.mark.parametrize("name", ["c1_sub", "c4_small", "c5_small", "mixture_small", "c5_dilute", "mixture4_small"])
 def test_adjoint_matches_autograd_reference(md, refs, name, prec):
     c, ref = refs[name]
     m = md.Model(c["model"])
