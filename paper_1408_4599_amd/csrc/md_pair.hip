@@ -2,18 +2,20 @@
 // (Sec. 2 interaction models; Sec. 3 linked cells, periodic boundaries, summation of forces and
 // torques per molecule).
 //
-// Work decomposition (one wavefront of 64 lanes per home cell):
-//   * the 27 cells around the home cell (edge >= r_c, so every partner inside the cutoff is
-//     there, Sec. 3) are staged into LDS with their periodic image shift already applied;
-//   * lanes are split into NI molecule lanes x NS = 64 / NI partner slices (NI = 16, 32 or 64
-//     from the home-cell occupancy), lane (i, s) scans staged partners s, s + NS, ...;
-//   * the COM cutoff test is done in FP64 with the exact expression
+// Work decomposition (details above each kernel):
+//   * the 27 cells around each home cell (edge >= r_c, so every partner inside the cutoff is
+//     there, Sec. 3) are staged into LDS with their periodic image shift already applied, shared
+//     by the wavefronts of a block (several home cells, or several wavefronts per dense cell);
+//   * the lanes of a wavefront are n molecules x NS = min(8, floor(64 / n)) partner slices, and
+//     lane (i, s) scans staged partners s, s + NS, ...;
+//   * pass 1 runs the COM cutoff test in FP64 with the exact expression
 //     fma(dz, dz, fma(dy, dy, dx * dx)) < r_c^2 on d = r_i - (r_j + shift), so the set of
-//     interacting pairs is the brute-force set bit for bit;
-//   * site-site arithmetic runs in R (float for MD_FP32, double for MD_FP64), per-molecule sums
-//     accumulate in FP64 and are reduced across the NS slices with cross-lane shuffles;
-//   * every home cell writes one row of block partials (energy, virial diagonal, pair count)
-//     which a deterministic two-stage reduction sums in a fixed order.
+//     interacting pairs is the brute-force set bit for bit, and lists the hits; pass 2 evaluates
+//     the listed pairs only;
+//   * the FP32 path (R = float) evaluates reciprocals, the LJ force scalar and the multipole
+//     terms in FP32; separations of LJ sites, pair energies and all per-molecule sums are FP64;
+//   * slices are combined in a fixed order; every block writes one row of partials (energy,
+//     virial diagonal, pair count) which a deterministic two-stage reduction sums in order.
 // Every pair is evaluated from both ends (full shell), so no atomics are needed and results are
 // bitwise reproducible.  The pair work is VALU-bound (no dense contraction: no MFMA).
 
@@ -65,10 +67,10 @@ template <typename R> struct LJAcc {
   }
 };
 
-// Fallback for a home cell whose neighbourhood does not fit the LDS tile (or holds more than 64
-// molecules): lanes of wave 0 are split into NI molecule lanes x NS partner slices over the 27
-// cells, staged through LDS in chunks of CAP, every staged partner tested.  Every thread of the
-// block must call it (it synchronises the block).
+// Path for a home cell with more than 64 molecules: lanes of wave 0 are split into NI molecule
+// lanes x NS partner slices over the 27 cells, staged through LDS in chunks of CAP, every staged
+// partner tested, 64 home molecules at a time.  Every thread of the block must call it (it
+// synchronises the block).
 template <typename R>
 __device__ void lj1_cell_chunked(const CellsDev &c, const LJPair &p, double rc2, const PairOut &o, int cell,
                                  double *jx, double *jy, double *jz, const int CAP, NbTable &nb, double acc5[5]) {
@@ -165,7 +167,7 @@ __device__ __forceinline__ void write_partial_block(double *partial, double acc5
   }
 }
 
-// Quad-cell kernel with compaction.  A block of four wavefronts takes 1 x 2 x 2 home cells (one in
+// Single-site kernel with compaction.  A block of four wavefronts takes 1 x 2 x 2 home cells (one in
 // x, two in y, two in z); their 27-cell neighbourhoods together span 3 x 4 x 4 cells, which are
 // staged once into LDS (image shifts applied) in x-fastest order.  In that order a wavefront's
 // stencil is three contiguous segments of nine cells (3 in x by 3 in y, one segment per z-layer).
