@@ -48,6 +48,34 @@ def distance_tests(counts3d):
     return float(nd.sum() - 0.5 * c.sum())
 
 
+# Algorithmic FLOP per unordered molecule pair inside the cutoff, counted from the interaction
+# formulas as written (Sec. 2 models; FMA = 2, reciprocal / reciprocal square root = 1,
+# compare = 0; each pair once).  Site pair terms include the site separation (6), r^2 (5), the
+# energy, the force vector on both molecules and the lever-arm torques on both (24); multipole
+# pairs add r-hat, the direction cosines, the energy's derivatives and the axis torques.
+LJ_ATOM_FLOP = 24          # single-site LJ pair: rcp, s^6, s^12, u, force scalar and vector, F_i F_j, U, W
+LJ_SITE_FLOP = 57
+ELEC_SITE_FLOP = {("C", "C"): 52, ("C", "D"): 88, ("C", "Q"): 94, ("D", "D"): 149, ("D", "Q"): 160,
+                  ("Q", "Q"): 175}
+VIRIAL_FLOP = 6            # r_ij . F_ij per molecule pair
+DIST_TEST_FLOP = 8         # 3 sub + 1 mul + 2 fma per half-shell distance test
+
+
+def pair_flops(model):
+    """Algorithmic FLOP per interacting molecule pair of a one-component model."""
+    sites = model["components"][0]["sites"]
+    if len(model["components"]) == 1 and len(sites) == 1 and sites[0]["kind"] == "lj":
+        return LJ_ATOM_FLOP
+    code = {"charge": "C", "dipole": "D", "quadrupole": "Q"}
+    nlj = sum(1 for x in sites if x["kind"] == "lj")
+    el = [code[x["kind"]] for x in sites if x["kind"] != "lj"]
+    f = nlj * nlj * LJ_SITE_FLOP + VIRIAL_FLOP
+    for a in el:
+        for b in el:
+            f += ELEC_SITE_FLOP[tuple(sorted((a, b)))]
+    return f
+
+
 def pair_counters(kernel_sources):
     """(HBM bytes, executed FP operations) per pair-kernel launch from the committed rocprofv3
     counter summary, if it was taken on the current kernel source (hash recorded in the summary);
@@ -85,6 +113,11 @@ def measure_extra(md, W, torch, name, evals, steps, adjoint=False):
     torch.cuda.synchronize()
     P = int(ref["npairs"].item())
     out["interacting_pairs"] = P
+    v = cells.view()
+    D = distance_tests(np.diff(v["cell_start"].cpu().numpy()).reshape(v["nc"][2], v["nc"][1], v["nc"][0]))
+    W_alg = DIST_TEST_FLOP * D + pair_flops(cfg["model"]) * P
+    out["algorithmic_flop_per_evaluation"] = W_alg
+    out["flop_per_pair"] = pair_flops(cfg["model"])
     for prec in ("fp32", "fp64"):
         buf = {"force": torch.empty((N, 3), dtype=torch.float64, device="cuda"),
                "uw": torch.empty(5, dtype=torch.float64, device="cuda"),
@@ -102,6 +135,7 @@ def measure_extra(md, W, torch, name, evals, steps, adjoint=False):
         ms, k = model.profile_read("pair")
         model.profile(False)
         e = {"forces_interactions_per_s": P / wall, "forces_ms": 1e3 * wall, "pair_kernel_ms": ms / k}
+        e["roofline_frac"] = W_alg / (ms / k / 1e3) / (PEAK_FP32 if prec == "fp32" else PEAK_FP64)
         if prec == "fp32":
             F32, F64 = buf["force"], ref["force"]
             e["force_rel_rms_vs_fp64"] = float(torch.linalg.norm(F32 - F64) / torch.linalg.norm(F64))
@@ -280,7 +314,7 @@ def main():
     ms_per_step = 1e3 * t32 / args.steps
     value = P * args.steps / t32
     E = e32[:, 0] + e32[:, 1] + e32[:, 2]
-    W_alg = 8.0 * D + 24.0 * P
+    W_alg = DIST_TEST_FLOP * D + pair_flops(cfg["model"]) * P
     traffic, executed = pair_counters(["md_pair.hip", "md_device.h", "md_internal.h"])
     out = {
         "metric": METRIC,
@@ -310,7 +344,8 @@ def main():
                      "traffic": traffic,
                      "kernel": "k_pair_lj1<float>" if model.single_site else "k_pair_ms<float>",
                      "algorithmic_flop_per_launch": W_alg,
-                     "accounting": "8 FLOP per half-shell distance test (D) + 24 FLOP per unique interacting pair (P)",
+                     "accounting": f"{DIST_TEST_FLOP} FLOP per half-shell distance test (D) + "
+                                   f"{pair_flops(cfg['model'])} FLOP per unique interacting pair (P)",
                      "frac_of_nonpacked_fp32_issue": W_alg / f32_pair / (PEAK_FP32 / 2),
                      "executed_flop_per_launch": executed,
                      "executed_frac": None if executed is None else executed / f32_pair / PEAK_FP32},
