@@ -154,9 +154,9 @@ def test_forces_fp64_match_oracle(md, oracle, name):
 # parameters, LJ site separations are FP64, so the FP32 rounding left in U is random, not
 # systematic.
 FP32_BARS = {name: (1e-5, 1e-5, 1e-9) for name in FORCE_CASES}
-# Four components, dilute: about 4e4 off-centre charge-charge terms per evaluation cancel to a
-# small U, and each carries the FP32 rounding of its world-frame site offsets (~1.5e-8 absolute);
-# measured 1.4e-9.
+# Four components, dilute: the charge-charge and charge-dipole terms of neutral molecules cancel
+# to a small U, and each keeps the FP32 rounding of its direction cosines and world-frame site
+# vectors (FP64 site offsets alone were tried and did not change it); measured 1.4e-9.
 FP32_BARS["mixture4_small"] = (1e-5, 1e-5, 2e-9)
 
 
