@@ -20,6 +20,7 @@
 // bitwise reproducible.  The pair work is VALU-bound (no dense contraction: no MFMA).
 
 #include <algorithm>
+#include <cmath>
 #include <type_traits>
 
 #include "md_device.h"
@@ -195,8 +196,9 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
   __shared__ int qoff[QCELLS + 1], qstart[QCELLS];
   __shared__ double qsh[QCELLS][3];
   __shared__ int scnt[4][64];
-  __shared__ NbTable nb;
   __shared__ double red[4][5];
+  // neighbour table of the chunked path, in the (then unused) list area
+  NbTable &nb = *(NbTable *)list;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nby = (c.ny + 1) >> 1, nbz = (c.nz + 1) >> 1;
@@ -289,34 +291,53 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
         const int cq = (cap - 16) >> 2;
         const int C = (cq - 16) / (2 * NS) * (2 * NS);
         const int wb = tiled ? 0 : 3 * wave * cq;  // index into dyn of staged slot 0 (32-bit LDS math)
-        int cnt = 0;
+        // this lane's hit list: entry k at mylist[64 k], holding the LDS index (in doubles) of the
+        // staged candidate; lp is the next free entry
+        __attribute__((address_space(3))) unsigned short *const mylist =
+            (__attribute__((address_space(3))) unsigned short *)wlist + lane;
+        __attribute__((address_space(3))) unsigned short *lp = mylist;
+        __attribute__((address_space(3))) unsigned short *const lplim = mylist + 64 * (lcap - 2);
         // pass 2: the hits of a molecule (its NS lanes' lists, in slice order) are split into NS
         // contiguous equal parts, one per lane; each lane sums its part in order
         auto flush = [&]() {
+          const int cnt = (int)(lp - mylist) >> 6;
           scnt[wave][lane] = cnt;
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           if (act) {
-            int H = 0;
-            for (int s2 = 0; s2 < NS; ++s2) H += scnt[wave][il + s2 * hn];
-            const int q0 = H * sl / NS, q1 = H * (sl + 1) / NS;
-            int sp = 0, j = q0, csp = scnt[wave][il];
-            for (int q = q0; q < q1; ++q, ++j) {
-              while (j >= csp) j -= csp, ++sp, csp = scnt[wave][il + sp * hn];
-              const int u = wlist[il + sp * hn + 64 * j];
-              const int iu = wb + 3 * u;
-              const double dx = xi - lds[iu], dy = yi - lds[iu + 1], dz = zi - lds[iu + 2];
-              const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-              a.add(dx, dy, dz, r2, eps24, sig2, p.eps4, p.sig2);
+            unsigned H = 0;
+#pragma unroll
+            for (int s2 = 0; s2 < NSMAX; ++s2)
+              if (s2 < NS) H += (unsigned)scnt[wave][il + s2 * hn];
+            const unsigned q0 = H * (unsigned)sl / (unsigned)NS, q1 = H * (unsigned)(sl + 1) / (unsigned)NS;
+            if (q0 < q1) {
+              // locate hit q0: list sp, entry j
+              unsigned j = q0;
+              int sp = 0;
+              unsigned csp = (unsigned)scnt[wave][il];
+              while (j >= csp) j -= csp, ++sp, csp = (unsigned)scnt[wave][il + sp * hn];
+              int li = il + sp * hn + 64 * (int)j;
+              int iu = wlist[li];
+              for (unsigned q = q0; q < q1; ++q) {
+                const int cu = iu;
+                const double dx = xi - lds[cu], dy = yi - lds[cu + 1], dz = zi - lds[cu + 2];
+                // next hit: same list, or the first entry of the next non-empty list
+                if (q + 1 < q1) {
+                  ++j, li += 64;
+                  while (j >= csp) j = 0, ++sp, csp = (unsigned)scnt[wave][il + sp * hn], li = il + sp * hn;
+                  iu = wlist[li];
+                }
+                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                a.add(dx, dy, dz, r2, eps24, sig2, p.eps4, p.sig2);
+              }
             }
           }
-          cnt = 0;
+          lp = mylist;
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         };
-        unsigned short *mylist = wlist + lane;
         const int sla = act ? sl : 0;  // idle lanes walk with slice 0
         for (int d = 0; d < 3; ++d) {
           const int u0 = 3 * hy + 12 * (hz + d);
@@ -347,7 +368,6 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
               int ia = wb + 3 * (cs + sla - off);  // running LDS index of candidate a
               for (int kb = cs; tail ? kb < ce : kb + 2 * NS <= ce; kb += 2 * NS, ia += 6 * NS) {
                 const int ta = kb + sla, tb = ta + NS;
-                const int sa = ta - off, sb = tb - off;
                 const int ib = ia + 3 * NS;
                 const double ax = xi - lds[ia], ay = yi - lds[ia + 1], az = zi - lds[ia + 2];
                 const double bx_ = xi - lds[ib], by_ = yi - lds[ib + 1], bz_ = zi - lds[ib + 2];
@@ -357,11 +377,11 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
                 if (tail) ha = ha && ta < ce, hb = hb && tb < ce;
                 if (home) ha = ha && ta != self, hb = hb && tb != self;
                 // the slot is always written; the count advances on a hit
-                mylist[64 * cnt] = (unsigned short)sa;
-                cnt += ha ? 1 : 0;
-                mylist[64 * cnt] = (unsigned short)sb;
-                cnt += hb ? 1 : 0;
-                if (__any(cnt > lcap - 2)) flush();
+                *lp = (unsigned short)ia;
+                lp += ha ? 64 : 0;
+                *lp = (unsigned short)ib;
+                lp += hb ? 64 : 0;
+                if (__any(lp > lplim)) flush();
                 if (tail) break;
               }
             };
@@ -424,15 +444,16 @@ inline int lj1_tile_cap(int64_t N, int64_t ncell) {
   return cap < 256 ? 256 : (cap > 4096 ? 4096 : cap);
 }
 
-// Per-lane hit-list length: expected partners per molecule (4/3 pi r_c^3 N/V) over the slices of
-// a lane, with margin; fuller lists are flushed early (pass 2) and restarted.
+// Per-lane hit-list length: the expected hits of a lane, h = (4/3 pi r_c^3 N/V) / NS, plus 2.5
+// Poisson standard deviations and 2, so that most wavefronts evaluate their hits once, at the end;
+// fuller lists are flushed early (pass 2) and restarted.
 inline int lj1_list_cap(int64_t N, double V, double rc, int64_t ncell) {
   const double mean = (double)N / (double)ncell;
   int NS = (int)(64.0 / (mean > 1.0 ? mean : 1.0));
   NS = NS < 1 ? 1 : (NS > NSMAX ? NSMAX : NS);
   const double hits = 4.18879020478639 * rc * rc * rc * (double)N / V / NS;
-  int l = (int)(1.25 * hits) + 4;
-  l = (l + 7) / 8 * 8;
+  int l = (int)std::ceil(hits + 2.5 * std::sqrt(hits) + 2.0);
+  l = (l + 3) / 4 * 4;
   return l < 16 ? 16 : (l > 64 ? 64 : l);
 }
 
