@@ -178,9 +178,10 @@ __device__ __forceinline__ void write_partial_block(double *partial, double acc5
 // test and appends hits to a per-lane list in LDS; when a list could overflow, the listed hits are
 // evaluated (pass 2) and the lists restart, so the pair arithmetic runs for partners inside the
 // cutoff only.  A block whose tile exceeds the LDS capacity walks the same candidates in the same
-// order through per-wavefront windows of its segments, so its results are bitwise those of the
-// staged tile; flushes may come earlier, which does not change the order of any sum.  Slice sums
-// are combined through LDS in a fixed order.  Home cells with more than 64 molecules use
+// order through per-wavefront windows of its segments: the same pairs, each evaluated the same
+// way.  Only the points where lists are flushed can differ (a window change flushes), which
+// regroups each molecule's sum over its lanes: a difference of rounding.  Slice sums are combined
+// through LDS in a fixed order.  Home cells with more than 64 molecules use
 // lj1_cell_chunked (a decision fixed by the configuration, not by the capacity).
 constexpr int QCELLS = 48;  // 3 x 4 x 4 staged cells
 constexpr int NSMAX = 8;
