@@ -353,7 +353,7 @@ def main():
                                "unit": "GB/s", "frac": build_bytes / build_s / PEAK_HBM,
                                "ms_per_build": 1e3 * build_s, "algorithmic_bytes_per_build": build_bytes,
                                "accounting": f"{build_bytes_mol:.0f} B per molecule + 4 B per cell",
-                               "kernels": "k_fill_i32, k_bin, k_scan_local/top/add, k_scatter, k_rank_gather"},
+                               "kernels": "k_bin, k_scan_local, k_scan_top, k_scatter, k_rank_gather"},
     }
     if not args.no_fp64:
         out["fp64"] = {"interactions_per_s": P * args.steps / t64, "ms_per_step": 1e3 * t64 / args.steps,

@@ -288,8 +288,8 @@ int md_cells_create(md_cells **out) {
 int md_cells_destroy(md_cells *c) {
   if (!c) return MD_OK;
   dfree(c->cell_of), dfree(c->slot), dfree(c->tmp), dfree(c->perm), dfree(c->perm_prev), dfree(c->scomp);
-  dfree(c->count), dfree(c->start), dfree(c->bsum);
-  dfree(c->sx), dfree(c->sy), dfree(c->sz), dfree(c->svec);
+  dfree(c->count), dfree(c->start), dfree(c->bsum), dfree(c->lstart);
+  dfree(c->sx), dfree(c->sy), dfree(c->sz), dfree(c->svec), dfree(c->wpos);
   delete c;
   return MD_OK;
 }
@@ -335,7 +335,8 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
         (cap = 0, rc = grow(c->tmp, cap, N, "tmp")) || (cap = 0, rc = grow(c->perm, cap, N, "perm")) ||
         (cap = 0, rc = grow(c->perm_prev, cap, N, "perm")) ||
         (cap = 0, rc = grow(c->scomp, cap, N, "scomp")) || (cap = 0, rc = grow(c->sx, cap, N, "sx")) ||
-        (cap = 0, rc = grow(c->sy, cap, N, "sy")) || (cap = 0, rc = grow(c->sz, cap, N, "sz"))) {
+        (cap = 0, rc = grow(c->sy, cap, N, "sy")) || (cap = 0, rc = grow(c->sz, cap, N, "sz")) ||
+        (cap = 0, rc = grow(c->wpos, cap, 3 * N, "wpos"))) {
       c->cap_N = 0;
       return rc;
     }
@@ -349,13 +350,17 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
   }
   if (ncell + 1 > capC) {
     int64_t cap = 0;
-    if ((rc = grow(c->count, cap, ncell + 1, "count")) || (cap = 0, rc = grow(c->start, cap, ncell + 1, "start")))
+    c->counts_zero = false;
+    c->cap_cell = 0;  // stays 0 if an allocation below fails, so the next build retries
+    if ((rc = grow(c->count, cap, ncell + 1, "count")) || (cap = 0, rc = grow(c->start, cap, ncell + 1, "start")) ||
+        (cap = 0, rc = grow(c->lstart, cap, ncell + 1, "lstart")))
       return rc;
     c->cap_cell = ncell + 1;
   }
   const int64_t nb = (ncell + 1023) / 1024 + 1;
   if (nb > capB) {
     int64_t cap = 0;
+    c->cap_blocks = 0;
     if ((rc = grow(c->bsum, cap, nb, "bsum"))) return rc;
     c->cap_blocks = nb;
   }
@@ -381,11 +386,15 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
   return sync_check(m, s);
 }
 
+// Pair kernel (+ the reduction of its block partials unless reduce is false: md_step reduces them
+// together with the leapfrog's kinetic-energy partials, which follow them in m->partial).
 static int forces_impl(md_model *m, const md_cells *c, int precision, double *force, double *torque, double *u_mol,
-                       double *w_mol, int32_t *nnb_mol, double *uw, int64_t *npairs, double *erow, hipStream_t s) {
+                       double *w_mol, int32_t *nnb_mol, double *uw, int64_t *npairs, double *erow, hipStream_t s,
+                       bool reduce = true, int64_t *nblocks_out = nullptr) {
   const int64_t nb = pair_blocks(c->ncell);
   int rc;
-  if ((rc = grow(m->partial, m->cap_partial, std::max<int64_t>(nb * PARTIAL_COLS, 2 * ((3 * c->N + 255) / 256 + (c->N + 255) / 256)), "partial")))
+  if ((rc = grow(m->partial, m->cap_partial,
+                 nb * PARTIAL_COLS + 2 * ((3 * c->N + 255) / 256 + (c->N + 255) / 256), "partial")))
     return rc;
   PairOut o{force, torque, u_mol, w_mol, nnb_mol, m->partial};
   int64_t nblocks = 0;
@@ -394,7 +403,8 @@ static int forces_impl(md_model *m, const md_cells *c, int precision, double *fo
   rc = launch_pair(m, c, precision, o, s, &nblocks);
   prof_end(m, PROF_PAIR, s, ev);
   if (rc) return rc;
-  return launch_reduce_forces(m, nblocks, m->partial, uw, npairs, erow, s);
+  if (nblocks_out) *nblocks_out = nblocks;
+  return reduce ? launch_reduce_forces(m, nblocks, m->partial, uw, npairs, erow, s) : MD_OK;
 }
 
 int md_forces(md_model *m, const md_cells *c, int precision, double *force, double *torque, double *u_mol,
@@ -429,13 +439,19 @@ int md_step(md_model *m, md_cells *c, double *pos, double *vel, double *quat, do
   for (int64_t st = 0; st < nsteps; ++st) {
     if ((rc = md_build_cells(m, c, pos, quat, comp, N, box, stream))) return rc;
     double *erow = energies ? energies + 4 * st : nullptr;
+    int64_t nbp = 0;
     if ((rc = forces_impl(m, c, precision, m->force, m->single_site ? nullptr : m->torque, nullptr, nullptr, nullptr,
-                          m->uw + 8, nullptr, erow, s)))
+                          m->uw + 8, nullptr, erow, s, false, &nbp)))
       return rc;
     hipEvent_t ev;
     prof_begin(m, PROF_STEP, s, &ev);
+    double *kin = m->partial + nbp * PARTIAL_COLS;  // after the pair partials
+    int64_t nkin = 0;
     rc = launch_leapfrog(m, pos, vel, quat, angmom, m->host.ncomp > 1 ? comp : nullptr, N, box, dt, m->force,
-                         m->torque, erow, s);
+                         m->torque, kin, &nkin, s);
+    // energies row: U, W from the pair partials and K_trans, K_rot from the leapfrog's, in one
+    // reduction (skipped when no energies are asked for)
+    if (!rc && erow) rc = launch_reduce_forces(m, nbp, m->partial, m->uw + 8, nullptr, erow, s, kin, nkin);
     prof_end(m, PROF_STEP, s, ev);
     if (rc) return rc;
   }

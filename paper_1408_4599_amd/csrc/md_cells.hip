@@ -5,6 +5,10 @@
 // HBM-bound: per molecule the build reads the COM (24 B), id/slot words and, for multi-site
 // models, the quaternion (32 B) and component id, and writes cell id, slot, permutation and the
 // sorted COM copy (24 B) plus site vectors.  Launch shapes are 256-thread blocks over molecules.
+// Five launches: bin (+ histogram), tile scan, scan of tile totals, scatter (+ final cell
+// starts), rank + gather.  The scan leaves the histogram zeroed for the next build.
+
+#include <algorithm>
 
 #include "md_internal.h"
 
@@ -23,12 +27,14 @@ struct BinArgs {
   double Lx, Ly, Lz, ihx, ihy, ihz;
   int32_t nx, ny, nz, ncomp, check_quat;
   int32_t *cell_of, *slot, *count, *status;
+  double *wpos;  // [N][3]: wrapped COM of the molecule visited by thread d, at 3 d
 };
 
 // Wrap + bin + per-cell histogram.  Thread d takes molecule order[d] (identity without an order):
 // with the previous build's permutation, neighbouring threads mostly fall into the same cell, and
 // each run of equal cells inside a wavefront takes one atomic add.  The slot it returns is only a
-// provisional position; the final order inside a cell is fixed by k_rank_gather.
+// provisional position; the final order inside a cell is fixed by k_rank_gather.  The wrapped COM
+// is kept in visiting order, so the gather reads it sequentially.
 __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
@@ -50,9 +56,10 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
     if (!(fabs(n2 - 1.0) <= 1e-6)) flags |= MD_DEV_QUAT;
   }
   if (flags && valid) atomicOr(a.status, flags);
-  const int cx = bin1(wrap1(x, a.Lx), a.ihx, a.nx);
-  const int cy = bin1(wrap1(y, a.Ly), a.ihy, a.ny);
-  const int cz = bin1(wrap1(z, a.Lz), a.ihz, a.nz);
+  const double xw = wrap1(x, a.Lx), yw = wrap1(y, a.Ly), zw = wrap1(z, a.Lz);
+  const int cx = bin1(xw, a.ihx, a.nx);
+  const int cy = bin1(yw, a.ihy, a.ny);
+  const int cz = bin1(zw, a.ihz, a.nz);
   const int cell = valid ? (cz * a.ny + cy) * a.nx + cx : -1;
   // runs of equal cells among consecutive lanes: the run head adds the run length
   const int prev = __shfl_up(cell, 1, 64);
@@ -68,6 +75,7 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
   if (valid) {
     a.cell_of[i] = cell;
     a.slot[i] = base + (lane - hl);
+    a.wpos[3 * d] = xw, a.wpos[3 * d + 1] = yw, a.wpos[3 * d + 2] = zw;
   }
 }
 
@@ -86,9 +94,9 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
-// Block-local exclusive scan of a tile of SCAN_TILE counts; the tile total goes to bsum[b].
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_local(const int32_t *in, int64_t n, int32_t *out,
-                                                             int32_t *bsum) {
+// Block-local exclusive scan of a tile of SCAN_TILE counts; the tile total goes to bsum[b].  The
+// counts are zeroed once read (the histogram of the next build starts from zero).
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_local(int32_t *in, int64_t n, int32_t *out, int32_t *bsum) {
   __shared__ int wsum[SCAN_THREADS / 64];
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
   int v[SCAN_ITEMS];
@@ -98,6 +106,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_local(const int32_t *in, 
     v[k] = (base + k < n) ? in[base + k] : 0;
     tsum += v[k];
   }
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k)
+    if (base + k < n) in[base + k] = 0;
   const int incl = wave_incl_scan(tsum);
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 63) wsum[w] = incl;
@@ -138,25 +149,24 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(int32_t *bsum, int64_
   if (threadIdx.x == 0) out[n] = carry_s;
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_add(int32_t *out, int64_t n, const int32_t *bsum) {
-  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-  const int add = bsum[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k)
-    if (base + k < n) out[base + k] += add;
-}
-
 // ---------------------------------------------------------------- stable placement + gather
-__global__ __launch_bounds__(256) void k_scatter(const int32_t *cell_of, const int32_t *slot, const int32_t *start,
-                                                 int64_t N, int32_t *tmp) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  tmp[start[cell_of[i]] + slot[i]] = (int32_t)i;
+// Cell start = tile-local prefix + scanned tile total: thread t < ncell writes start[t]; thread
+// i < N places molecule i at its provisional slot of its cell (both read only lstart and bsum).
+__global__ __launch_bounds__(256) void k_scatter(const int32_t *cell_of, const int32_t *slot, const int32_t *lstart,
+                                                 const int32_t *bsum, int64_t N, int64_t ncell, int32_t *start,
+                                                 int32_t *tmp) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ncell) start[t] = lstart[t] + bsum[t / SCAN_TILE];
+  if (t < N) {
+    const int c = cell_of[t];
+    tmp[lstart[c] + bsum[c / SCAN_TILE] + slot[t]] = (int32_t)t;
+  }
 }
 
 struct GatherArgs {
-  const double *pos, *quat;
+  const double *quat;
   const int32_t *comp, *cell_of, *start, *tmp, *order;
+  const double *wpos;
   int64_t N;
   double Lx, Ly, Lz;
   const ModelDev *md;
@@ -175,8 +185,9 @@ __device__ __forceinline__ void rotate(const double q[4], const double v[3], dou
 // Final position of molecule i inside its cell = number of molecules of the same cell with a
 // smaller original index (a stable counting sort whatever order the atomic slots came in); then
 // gather the sorted copies.  The cell's entries are contiguous in tmp, so the ranking reads
-// cached words only.  Thread d takes molecule order[d] (identity without an order): in the
-// previous build's order the sorted copies are written nearly in sequence.
+// cached words only.  Thread d takes molecule order[d] (identity without an order), the visiting
+// order of k_bin, whose wrapped COM it reads in sequence; in the previous build's order the sorted
+// copies are written nearly in sequence.
 __global__ __launch_bounds__(256) void k_rank_gather(GatherArgs a) {
   const int64_t dd = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (dd >= a.N) return;
@@ -187,11 +198,9 @@ __global__ __launch_bounds__(256) void k_rank_gather(GatherArgs a) {
   for (int k = 0; k < n; ++k) rank += a.tmp[s + k] < (int32_t)i ? 1 : 0;
   const int d = s + rank;
   a.perm[d] = (int32_t)i;
-  double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
-  if (!(isfinite(x) && isfinite(y) && isfinite(z))) x = y = z = 0.0;
-  a.sx[d] = wrap1(x, a.Lx);
-  a.sy[d] = wrap1(y, a.Ly);
-  a.sz[d] = wrap1(z, a.Lz);
+  a.sx[d] = a.wpos[3 * dd];
+  a.sy[d] = a.wpos[3 * dd + 1];
+  a.sz[d] = a.wpos[3 * dd + 2];
   int ci = 0;
   if (a.comp) {
     ci = a.comp[i];
@@ -274,23 +283,28 @@ int launch_scale_copy(const double *src, double *dst, int64_t n, double a, hipSt
 int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat, const int32_t *comp, int64_t N,
                  const double inv_h[3], const int32_t *order, hipStream_t s) {
   int rc;
-  if ((rc = launch_fill_i32(c->count, c->ncell, 0, s))) return rc;
+  // the histogram must start at zero: left so by the previous build's scan, else cleared here
+  // (whole allocation, so a later build with more cells also starts from zero)
+  if (!c->counts_zero && (rc = launch_fill_i32(c->count, c->cap_cell, 0, s))) return rc;
+  c->counts_zero = false;
   BinArgs b{pos,      quat,      comp,      order,     N,        c->box[0],       c->box[1],
             c->box[2], inv_h[0], inv_h[1], inv_h[2], c->nc[0],        c->nc[1],
             c->nc[2], m->host.ncomp, (int32_t)((m->flags & MD_CHECK) != 0), c->cell_of, c->slot, c->count,
-            m->status};
+            m->status, c->wpos};
   k_bin<<<nblk(N, 256), 256, 0, s>>>(b);
   if ((rc = check_hip(hipGetLastError(), "k_bin"))) return rc;
   const int64_t nb = (c->ncell + SCAN_TILE - 1) / SCAN_TILE;
-  k_scan_local<<<(unsigned)nb, SCAN_THREADS, 0, s>>>(c->count, c->ncell, c->start, c->bsum);
+  k_scan_local<<<(unsigned)nb, SCAN_THREADS, 0, s>>>(c->count, c->ncell, c->lstart, c->bsum);
   k_scan_top<<<1, SCAN_THREADS, 0, s>>>(c->bsum, nb, c->start, c->ncell);
-  k_scan_add<<<(unsigned)nb, SCAN_THREADS, 0, s>>>(c->start, c->ncell, c->bsum);
   if ((rc = check_hip(hipGetLastError(), "k_scan"))) return rc;
-  k_scatter<<<nblk(N, 256), 256, 0, s>>>(c->cell_of, c->slot, c->start, N, c->tmp);
+  c->counts_zero = true;
+  k_scatter<<<nblk(std::max<int64_t>(N, c->ncell), 256), 256, 0, s>>>(c->cell_of, c->slot, c->lstart, c->bsum, N,
+                                                                      c->ncell, c->start, c->tmp);
   if ((rc = check_hip(hipGetLastError(), "k_scatter"))) return rc;
-  GatherArgs g{pos, m->single_site ? nullptr : quat, comp, c->cell_of, c->start, c->tmp, order, N, c->box[0], c->box[1],
-               c->box[2], m->dev, m->shape.lj, m->shape.chg, m->shape.dip, m->shape.quad, c->nvec, c->perm,
-               m->single_site ? nullptr : c->scomp, c->sx, c->sy, c->sz, m->single_site ? nullptr : c->svec};
+  GatherArgs g{m->single_site ? nullptr : quat, comp, c->cell_of, c->start, c->tmp, order, c->wpos, N,
+               c->box[0], c->box[1], c->box[2], m->dev, m->shape.lj, m->shape.chg, m->shape.dip, m->shape.quad,
+               c->nvec, c->perm, m->single_site ? nullptr : c->scomp, c->sx, c->sy, c->sz,
+               m->single_site ? nullptr : c->svec};
   k_rank_gather<<<nblk(N, 256), 256, 0, s>>>(g);
   return check_hip(hipGetLastError(), "k_rank_gather");
 }

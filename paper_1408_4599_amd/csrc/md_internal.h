@@ -94,7 +94,10 @@ struct md_cells {
   int32_t *cell_of = nullptr, *slot = nullptr, *tmp = nullptr, *perm = nullptr, *scomp = nullptr;
   int32_t *perm_prev = nullptr;  // the other buffer of the permutation pair (previous build's order)
   int32_t *count = nullptr, *start = nullptr, *bsum = nullptr;
+  int32_t *lstart = nullptr;     // tile-local exclusive prefix of the counts
+  bool counts_zero = false;      // every entry of the count allocation is zero (left so by the scan)
   double *sx = nullptr, *sy = nullptr, *sz = nullptr, *svec = nullptr;
+  double *wpos = nullptr;        // [N][3] wrapped COMs in the visiting order of the build
 };
 
 struct md_model {
@@ -143,11 +146,15 @@ int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat
                  const double inv_h[3], const int32_t *order, hipStream_t s);
 int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o, hipStream_t s, int64_t *nblocks);
 int launch_reduce(md_model *m, int64_t nrows, int ncols, const double *rows, double *out, hipStream_t s);
+// pair partial rows -> U, W, W_aa, pair count, energies row; with kin_rows (the leapfrog's
+// [kin_nrows][2] kinetic-energy partials) also K_trans and K_rot of the energies row
 int launch_reduce_forces(md_model *m, int64_t nrows, const double *rows, double *uw, int64_t *npairs,
-                         double *energies_row, hipStream_t s);
+                         double *energies_row, hipStream_t s, const double *kin_rows = nullptr,
+                         int64_t kin_nrows = 0);
+// leapfrog step; writes its kinetic-energy partial rows ([*kin_nrows][2]) to kin_rows
 int launch_leapfrog(md_model *m, double *pos, double *vel, double *quat, double *angmom, const int32_t *comp,
                     int64_t N, const double box[3], double dt, const double *force, const double *torque,
-                    double *energies_row, hipStream_t s);
+                    double *kin_rows, int64_t *kin_nrows, hipStream_t s);
 int launch_adjoint(md_model *m, const md_cells *c, int precision, const AdjOut &o, const double *quat,
                    hipStream_t s, int64_t *nblocks);
 int launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);

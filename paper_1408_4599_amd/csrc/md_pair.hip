@@ -799,11 +799,13 @@ constexpr int RED_THREADS = 256;
 constexpr int RED_BLOCKS = 256;
 constexpr int RED_MAXCOLS = 256;
 
-// Column sums of a [nrows][ncols] table in two launches.  Stage 1: block b sums rows
-// [b chunk, (b + 1) chunk), thread t taking rows t, t + 256, ... in order, then a fixed LDS tree,
-// into red2[b].  Stage 2 (one block) sums red2 over b in the same way and writes the result, for
-// the force sums also U, W, W_aa, the pair count and the energies row.  The summation order never
-// depends on timing.
+// Column sums of a [nrows][ncols] table (optionally followed by the columns of a second table
+// [nrows2][ncols2]) in two launches.  Stage 1: block b sums rows [b chunk, (b + 1) chunk), thread
+// t taking rows t, t + 256, ... in order, then a fixed LDS tree, into red2[b]; the same for the
+// second table with its own chunk.  Stage 2 (one block) sums red2 over b in the same way and writes
+// the result, for the force sums also U, W, W_aa, the pair count and the energies row (with the
+// kinetic energies of the leapfrog as the second table).  The summation order never depends on
+// timing.
 __device__ __forceinline__ double block_tree(double v, double *sh) {
   const int t = threadIdx.x;
   sh[t] = v;
@@ -818,15 +820,25 @@ __device__ __forceinline__ double block_tree(double v, double *sh) {
 }
 
 __global__ __launch_bounds__(RED_THREADS) void k_reduce_cols(const double *rows, int64_t nrows, int ncols,
-                                                             int64_t chunk, double *out) {
+                                                             int64_t chunk, const double *rows2, int64_t nrows2,
+                                                             int ncols2, int64_t chunk2, double *out) {
   __shared__ double sh[RED_THREADS];
+  const int nc = ncols + ncols2;
   const int64_t r0 = (int64_t)blockIdx.x * chunk;
   const int64_t r1 = min(nrows, r0 + chunk);
   for (int col = 0; col < ncols; ++col) {
     double v = 0.0;
     for (int64_t r = r0 + threadIdx.x; r < r1; r += RED_THREADS) v += rows[r * ncols + col];
     v = block_tree(v, sh);
-    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * ncols + col] = v;
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * nc + col] = v;
+  }
+  const int64_t q0 = (int64_t)blockIdx.x * chunk2;
+  const int64_t q1 = min(nrows2, q0 + chunk2);
+  for (int col = 0; col < ncols2; ++col) {
+    double v = 0.0;
+    for (int64_t r = q0 + threadIdx.x; r < q1; r += RED_THREADS) v += rows2[r * ncols2 + col];
+    v = block_tree(v, sh);
+    if (threadIdx.x == 0) out[(int64_t)blockIdx.x * nc + ncols + col] = v;
   }
 }
 
@@ -846,6 +858,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double *red2
     uw[0] = U, uw[1] = W, uw[2] = res[1], uw[3] = res[2], uw[4] = res[3];
     if (npairs) *npairs = (int64_t)(res[4] * 0.5);
     if (erow) erow[0] = U, erow[3] = W;
+    if (erow && ncols == PARTIAL_COLS + 2) erow[1] = res[PARTIAL_COLS], erow[2] = res[PARTIAL_COLS + 1];
   } else {
     for (int col = 0; col < ncols; ++col) out[col] = res[col];
   }
@@ -911,16 +924,20 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
 int launch_reduce(md_model *m, int64_t nrows, int ncols, const double *rows, double *out, hipStream_t s) {
   if (ncols > RED_MAXCOLS) return set_error(MD_EINVAL, "reduction too wide");
   const int64_t chunk = (nrows + RED_BLOCKS - 1) / RED_BLOCKS;
-  k_reduce_cols<<<RED_BLOCKS, RED_THREADS, 0, s>>>(rows, nrows, ncols, chunk > 0 ? chunk : 1, m->red2);
+  k_reduce_cols<<<RED_BLOCKS, RED_THREADS, 0, s>>>(rows, nrows, ncols, chunk > 0 ? chunk : 1, nullptr, 0, 0, 1,
+                                                   m->red2);
   k_reduce_final<<<1, RED_THREADS, 0, s>>>(m->red2, RED_BLOCKS, ncols, out, 0, nullptr, nullptr, nullptr);
   return check_hip(hipGetLastError(), "k_reduce");
 }
 
 int launch_reduce_forces(md_model *m, int64_t nrows, const double *rows, double *uw, int64_t *npairs, double *erow,
-                         hipStream_t s) {
+                         hipStream_t s, const double *kin_rows, int64_t kin_nrows) {
   const int64_t chunk = (nrows + RED_BLOCKS - 1) / RED_BLOCKS;
-  k_reduce_cols<<<RED_BLOCKS, RED_THREADS, 0, s>>>(rows, nrows, PARTIAL_COLS, chunk > 0 ? chunk : 1, m->red2);
-  k_reduce_final<<<1, RED_THREADS, 0, s>>>(m->red2, RED_BLOCKS, PARTIAL_COLS, nullptr, 1, uw, npairs, erow);
+  const int kc = kin_rows ? 2 : 0;
+  const int64_t chunk2 = (kin_nrows + RED_BLOCKS - 1) / RED_BLOCKS;
+  k_reduce_cols<<<RED_BLOCKS, RED_THREADS, 0, s>>>(rows, nrows, PARTIAL_COLS, chunk > 0 ? chunk : 1, kin_rows,
+                                                   kc ? kin_nrows : 0, kc, chunk2 > 0 ? chunk2 : 1, m->red2);
+  k_reduce_final<<<1, RED_THREADS, 0, s>>>(m->red2, RED_BLOCKS, PARTIAL_COLS + kc, nullptr, 1, uw, npairs, erow);
   return check_hip(hipGetLastError(), "k_reduce");
 }
 

@@ -124,18 +124,16 @@ __global__ __launch_bounds__(256) void k_leapfrog_rot(LeapArgs a, int64_t row0) 
 
 int launch_leapfrog(md_model *m, double *pos, double *vel, double *quat, double *angmom, const int32_t *comp,
                     int64_t N, const double box[3], double dt, const double *force, const double *torque,
-                    double *energies_row, hipStream_t s) {
+                    double *kin_rows, int64_t *kin_nrows, hipStream_t s) {
   const int64_t nt = (3 * N + 255) / 256;
   const bool rot = !m->single_site && quat && angmom;
   const int64_t nr = rot ? (N + 255) / 256 : 0;
   LeapArgs a{pos, vel, rot ? quat : nullptr, rot ? angmom : nullptr, comp, N, box[0], box[1],
-             box[2], dt, force, torque, m->dev, m->partial};
+             box[2], dt, force, torque, m->dev, kin_rows};
   k_leapfrog_trans<<<(unsigned)nt, 256, 0, s>>>(a);
   if (rot) k_leapfrog_rot<<<(unsigned)nr, 256, 0, s>>>(a, nt);
-  int rc = check_hip(hipGetLastError(), "k_leapfrog");
-  if (rc) return rc;
-  if (energies_row) return launch_reduce(m, nt + nr, 2, m->partial, energies_row + 1, s);
-  return MD_OK;
+  *kin_nrows = nt + nr;
+  return check_hip(hipGetLastError(), "k_leapfrog");
 }
 
 }  // namespace mdcell
