@@ -89,6 +89,27 @@ def test_cells_rebuild_in_previous_order(md, oracle):
         np.testing.assert_array_equal(fa[k].cpu().numpy(), fb[k].cpu().numpy())
 
 
+def test_cells_one_object_across_grids(md, oracle):
+    """One cells object rebuilt for grids of changing size (reallocation, then fewer and more cells
+    without reallocation, then the same N in another box): every build must equal the oracle's
+    binning and stable order.  The histogram is left zeroed by each build for the next one."""
+    m = md.Model(W.lj_model(2.5))
+    cells = md.Cells()
+    seq = [(2000, [10.0, 12.5, 15.0], 1), (6000, [20.0, 20.0, 20.0], 2), (1500, [10.0, 10.0, 10.0], 3),
+           (3000, [15.0, 17.5, 20.0], 4), (3000, [20.0, 20.0, 20.0], 5), (3000, [10.0, 10.0, 12.5], 6)]
+    for N, box, seed in seq:
+        pos = W.random_gas(N, box, W.lj_model(2.5), seed=seed)["pos"]
+        md.build_cells(m, cells, dev(pos), None, None, box)
+        ref_cell, _, ncell = oracle.bin_cells(pos, box, 2.5)
+        v = cells.view()
+        assert v["ncell"] == ncell
+        np.testing.assert_array_equal(v["cell_of"].cpu().numpy(), ref_cell)
+        start = v["cell_start"].cpu().numpy()
+        np.testing.assert_array_equal(np.diff(start), np.bincount(ref_cell, minlength=ncell))
+        assert start[0] == 0 and start[-1] == N
+        np.testing.assert_array_equal(v["perm"].cpu().numpy(), np.lexsort((np.arange(N), ref_cell)))
+
+
 FORCE_CASES = ["c1_ljts_4000", "c3_small", "c4_small", "c5_small", "mixture_small", "gas_ragged", "one_cell",
                "c5_dilute", "mixture_dilute", "mixture4_small"]
 
