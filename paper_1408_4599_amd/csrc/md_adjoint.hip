@@ -33,6 +33,7 @@ template <int SL, int SC, int SD, int SQ> struct AdjAcc {
 template <int KA, int KB, int SL, int SC, int SD, int SQ, bool MIX, typename R>
 __device__ __forceinline__ void adj_elec_group(const CompDev &A, const CompDev &B, const R (*vi)[3], const R *vj,
                                                R dx, R dy, R dz, R krc3, AdjAcc<SL, SC, SD, SQ> &acc) {
+#pragma clang fp contract(fast)  // products and sums fused where the compiler can (pair algebra only)
   using S = Slots<SL, SC, SD, SQ>;
   constexpr int NA = KA == KIND_CHG ? SC : (KA == KIND_DIP ? SD : SQ);
   constexpr int NB = KB == KIND_CHG ? SC : (KB == KIND_DIP ? SD : SQ);
@@ -86,6 +87,7 @@ __device__ __forceinline__ void adj_elec_group(const CompDev &A, const CompDev &
 template <int SL, int SC, int SD, int SQ, bool MIX, typename R>
 __device__ __forceinline__ void adj_pair(const ModelDev *__restrict__ md, int ci, int cj, const R (*vi)[3],
                                          const R *vj, R dx, R dy, R dz, AdjAcc<SL, SC, SD, SQ> &acc) {
+#pragma clang fp contract(fast)
   const CompDev &A = md->comp[ci];
   const CompDev &B = md->comp[cj];
   const int nla = MIX ? A.n_lj : SL, nlb = MIX ? B.n_lj : SL;
@@ -210,8 +212,8 @@ template <int SL, int SC, int SD, int SQ> struct PSlots {
 // site terms into the lane's adjoint accumulators (the hits of a molecule split evenly over its
 // slice lanes), slices are then added in a fixed order.
 template <typename R, int SL, int SC, int SD, int SQ, bool MIX, bool SINGLE, int CAP, int W>
-__global__ __launch_bounds__(64 * W) void k_adjoint(CellsDev c, const ModelDev *__restrict__ md, const double *quat,
-                                                    double rc2, AdjOut o) {
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 : 3))) void k_adjoint(
+    CellsDev c, const ModelDev *__restrict__ md, const double *quat, double rc2, AdjOut o) {
   using S = Slots<SL, SC, SD, SQ>;
   using Acc = AdjAcc<SL, SC, SD, SQ>;
   using PS = PSlots<SL, SC, SD, SQ>;

@@ -143,6 +143,7 @@ template <int KA, int KB> constexpr int unit_rpow() {
 
 template <int KA, int KB, typename R>
 __device__ __forceinline__ Unit<R> unit_terms(R ir, R ci, R cj, R cij, R krc3) {
+#pragma clang fp contract(fast)  // products and sums fused where the compiler can (pair algebra only)
   Unit<R> u{0, 0, 0, 0, 0, 0, 0};
   const R ir2 = ir * ir, ir3 = ir2 * ir, ir4 = ir3 * ir;
   if constexpr (KA == KIND_CHG && KB == KIND_CHG) {
@@ -180,7 +181,11 @@ __device__ __forceinline__ Unit<R> unit_terms(R ir, R ci, R cj, R cij, R krc3) {
     u.tij = ir3 - krc3;
   } else if constexpr (KA == KIND_DIP && KB == KIND_QUAD) {
     const R p = (R)1.5 * ir4;
-    const R g = ci - (R)5 * ci * cj * cj + (R)2 * cj * cij;
+    R g;
+    {
+#pragma clang fp contract(off)  // the angular factor of the energy keeps its unfused rounding
+      g = ci - (R)5 * ci * cj * cj + (R)2 * cj * cij;
+    }
     u.ang = (R)1.5 * g;
     u.t = p * g;
     u.tr = (R)-4 * u.t * ir;
@@ -189,7 +194,11 @@ __device__ __forceinline__ Unit<R> unit_terms(R ir, R ci, R cj, R cij, R krc3) {
     u.tij = p * (R)2 * cj;
   } else if constexpr (KA == KIND_QUAD && KB == KIND_DIP) {
     const R p = (R)-1.5 * ir4;
-    const R g = cj - (R)5 * cj * ci * ci + (R)2 * ci * cij;
+    R g;
+    {
+#pragma clang fp contract(off)
+      g = cj - (R)5 * cj * ci * ci + (R)2 * ci * cij;
+    }
     u.ang = (R)-1.5 * g;
     u.t = p * g;
     u.tr = (R)-4 * u.t * ir;
@@ -200,8 +209,13 @@ __device__ __forceinline__ Unit<R> unit_terms(R ir, R ci, R cj, R cij, R krc3) {
     const R p = (R)0.75 * ir4 * ir;
     const R s = fma((R)-5 * ci, cj, cij);
     const R ci2 = ci * ci, cj2 = cj * cj;
-    u.ang = (R)0.75 * ((R)1 - (R)5 * ci2 - (R)5 * cj2 - (R)15 * ci2 * cj2 + (R)2 * s * s);
-    u.t = p * ((R)1 - (R)5 * ci2 - (R)5 * cj2 - (R)15 * ci2 * cj2 + (R)2 * s * s);
+    R g;
+    {
+#pragma clang fp contract(off)
+      g = (R)1 - (R)5 * ci2 - (R)5 * cj2 - (R)15 * ci2 * cj2 + (R)2 * s * s;
+    }
+    u.ang = (R)0.75 * g;
+    u.t = p * g;
     u.tr = (R)-5 * u.t * ir;
     u.ti = p * ((R)-10 * ci - (R)30 * ci * cj2 - (R)20 * cj * s);
     u.tj = p * ((R)-10 * cj - (R)30 * cj * ci2 - (R)20 * ci * s);

@@ -464,6 +464,7 @@ inline int lj1_list_cap(int64_t N, double V, double rc, int64_t ncell) {
 // =====================================================================================
 
 template <typename R> __device__ __forceinline__ void cross_acc(R *T, const R *a, const R *f) {
+#pragma clang fp contract(fast)
   T[0] += a[1] * f[2] - a[2] * f[1];
   T[1] += a[2] * f[0] - a[0] * f[2];
   T[2] += a[0] * f[1] - a[1] * f[0];
@@ -482,6 +483,7 @@ template <int KA, int KB, typename R>
 __device__ __forceinline__ void elec_site(R pm, double pmd, const R *oa, const R *ea, const R *ob, const R *eb, R dx,
                                           R dy, R dz, double dxd, double dyd, double dzd, R krc3, double krc3d,
                                           PairAcc<R> &acc) {
+#pragma clang fp contract(fast)
   const R rx = dx + oa[0] - ob[0], ry = dy + oa[1] - ob[1], rz = dz + oa[2] - ob[2];
   const R r2 = fma(rz, rz, fma(ry, ry, rx * rx));
   const R ir = rsq_nr<R>(r2);
@@ -569,6 +571,7 @@ template <int SL, int SC, int SD, int SQ, bool MIX, typename R>
 __device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci, int cj, const double (*vil)[3],
                                          const R (*vi)[3], const double *vjl, const R *vje, double dxd, double dyd,
                                          double dzd, PairAcc<R> &acc) {
+#pragma clang fp contract(fast)
   const CompDev &A = md->comp[ci];
   const CompDev &B = md->comp[cj];
   const int nla = MIX ? A.n_lj : SL, nlb = MIX ? B.n_lj : SL;
