@@ -289,7 +289,7 @@ int md_cells_destroy(md_cells *c) {
   if (!c) return MD_OK;
   dfree(c->cell_of), dfree(c->slot), dfree(c->tmp), dfree(c->perm), dfree(c->perm_prev), dfree(c->scomp);
   dfree(c->count), dfree(c->start), dfree(c->bsum), dfree(c->lstart);
-  dfree(c->sx), dfree(c->sy), dfree(c->sz), dfree(c->svec), dfree(c->wpos);
+  dfree(c->sx), dfree(c->sy), dfree(c->sz), dfree(c->svec);
   delete c;
   return MD_OK;
 }
@@ -335,8 +335,7 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
         (cap = 0, rc = grow(c->tmp, cap, N, "tmp")) || (cap = 0, rc = grow(c->perm, cap, N, "perm")) ||
         (cap = 0, rc = grow(c->perm_prev, cap, N, "perm")) ||
         (cap = 0, rc = grow(c->scomp, cap, N, "scomp")) || (cap = 0, rc = grow(c->sx, cap, N, "sx")) ||
-        (cap = 0, rc = grow(c->sy, cap, N, "sy")) || (cap = 0, rc = grow(c->sz, cap, N, "sz")) ||
-        (cap = 0, rc = grow(c->wpos, cap, 3 * N, "wpos"))) {
+        (cap = 0, rc = grow(c->sy, cap, N, "sy")) || (cap = 0, rc = grow(c->sz, cap, N, "sz"))) {
       c->cap_N = 0;
       return rc;
     }

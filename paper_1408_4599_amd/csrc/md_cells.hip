@@ -27,14 +27,12 @@ struct BinArgs {
   double Lx, Ly, Lz, ihx, ihy, ihz;
   int32_t nx, ny, nz, ncomp, check_quat;
   int32_t *cell_of, *slot, *count, *status;
-  double *wpos;  // [N][3]: wrapped COM of the molecule visited by thread d, at 3 d
 };
 
 // Wrap + bin + per-cell histogram.  Thread d takes molecule order[d] (identity without an order):
 // with the previous build's permutation, neighbouring threads mostly fall into the same cell, and
 // each run of equal cells inside a wavefront takes one atomic add.  The slot it returns is only a
-// provisional position; the final order inside a cell is fixed by k_rank_gather.  The wrapped COM
-// is kept in visiting order, so the gather reads it sequentially.
+// provisional position; the final order inside a cell is fixed by k_rank_gather.
 __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
@@ -56,10 +54,9 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
     if (!(fabs(n2 - 1.0) <= 1e-6)) flags |= MD_DEV_QUAT;
   }
   if (flags && valid) atomicOr(a.status, flags);
-  const double xw = wrap1(x, a.Lx), yw = wrap1(y, a.Ly), zw = wrap1(z, a.Lz);
-  const int cx = bin1(xw, a.ihx, a.nx);
-  const int cy = bin1(yw, a.ihy, a.ny);
-  const int cz = bin1(zw, a.ihz, a.nz);
+  const int cx = bin1(wrap1(x, a.Lx), a.ihx, a.nx);
+  const int cy = bin1(wrap1(y, a.Ly), a.ihy, a.ny);
+  const int cz = bin1(wrap1(z, a.Lz), a.ihz, a.nz);
   const int cell = valid ? (cz * a.ny + cy) * a.nx + cx : -1;
   // runs of equal cells among consecutive lanes: the run head adds the run length
   const int prev = __shfl_up(cell, 1, 64);
@@ -75,7 +72,6 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
   if (valid) {
     a.cell_of[i] = cell;
     a.slot[i] = base + (lane - hl);
-    a.wpos[3 * d] = xw, a.wpos[3 * d + 1] = yw, a.wpos[3 * d + 2] = zw;
   }
 }
 
@@ -164,9 +160,8 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t *cell_of, const i
 }
 
 struct GatherArgs {
-  const double *quat;
+  const double *pos, *quat;
   const int32_t *comp, *cell_of, *start, *tmp, *order;
-  const double *wpos;
   int64_t N;
   double Lx, Ly, Lz;
   const ModelDev *md;
@@ -185,9 +180,9 @@ __device__ __forceinline__ void rotate(const double q[4], const double v[3], dou
 // Final position of molecule i inside its cell = number of molecules of the same cell with a
 // smaller original index (a stable counting sort whatever order the atomic slots came in); then
 // gather the sorted copies.  The cell's entries are contiguous in tmp, so the ranking reads
-// cached words only.  Thread d takes molecule order[d] (identity without an order), the visiting
-// order of k_bin, whose wrapped COM it reads in sequence; in the previous build's order the sorted
-// copies are written nearly in sequence.
+// cached words only.  Thread d takes molecule order[d] (identity without an order): in the
+// previous build's order the sorted copies are written nearly in sequence, and the COMs read are
+// the lines k_bin has just read in the same order.
 __global__ __launch_bounds__(256) void k_rank_gather(GatherArgs a) {
   const int64_t dd = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (dd >= a.N) return;
@@ -198,9 +193,11 @@ __global__ __launch_bounds__(256) void k_rank_gather(GatherArgs a) {
   for (int k = 0; k < n; ++k) rank += a.tmp[s + k] < (int32_t)i ? 1 : 0;
   const int d = s + rank;
   a.perm[d] = (int32_t)i;
-  a.sx[d] = a.wpos[3 * dd];
-  a.sy[d] = a.wpos[3 * dd + 1];
-  a.sz[d] = a.wpos[3 * dd + 2];
+  double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) x = y = z = 0.0;
+  a.sx[d] = wrap1(x, a.Lx);
+  a.sy[d] = wrap1(y, a.Ly);
+  a.sz[d] = wrap1(z, a.Lz);
   int ci = 0;
   if (a.comp) {
     ci = a.comp[i];
@@ -290,7 +287,7 @@ int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat
   BinArgs b{pos,      quat,      comp,      order,     N,        c->box[0],       c->box[1],
             c->box[2], inv_h[0], inv_h[1], inv_h[2], c->nc[0],        c->nc[1],
             c->nc[2], m->host.ncomp, (int32_t)((m->flags & MD_CHECK) != 0), c->cell_of, c->slot, c->count,
-            m->status, c->wpos};
+            m->status};
   k_bin<<<nblk(N, 256), 256, 0, s>>>(b);
   if ((rc = check_hip(hipGetLastError(), "k_bin"))) return rc;
   const int64_t nb = (c->ncell + SCAN_TILE - 1) / SCAN_TILE;
@@ -301,7 +298,7 @@ int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat
   k_scatter<<<nblk(std::max<int64_t>(N, c->ncell), 256), 256, 0, s>>>(c->cell_of, c->slot, c->lstart, c->bsum, N,
                                                                       c->ncell, c->start, c->tmp);
   if ((rc = check_hip(hipGetLastError(), "k_scatter"))) return rc;
-  GatherArgs g{m->single_site ? nullptr : quat, comp, c->cell_of, c->start, c->tmp, order, c->wpos, N,
+  GatherArgs g{pos, m->single_site ? nullptr : quat, comp, c->cell_of, c->start, c->tmp, order, N,
                c->box[0], c->box[1], c->box[2], m->dev, m->shape.lj, m->shape.chg, m->shape.dip, m->shape.quad,
                c->nvec, c->perm, m->single_site ? nullptr : c->scomp, c->sx, c->sy, c->sz,
                m->single_site ? nullptr : c->svec};

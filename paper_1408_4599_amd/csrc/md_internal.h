@@ -97,7 +97,6 @@ struct md_cells {
   int32_t *lstart = nullptr;     // tile-local exclusive prefix of the counts
   bool counts_zero = false;      // every entry of the count allocation is zero (left so by the scan)
   double *sx = nullptr, *sy = nullptr, *sz = nullptr, *svec = nullptr;
-  double *wpos = nullptr;        // [N][3] wrapped COMs in the visiting order of the build
 };
 
 struct md_model {
