@@ -461,10 +461,15 @@ static void om_qadvance(const double *q, const double *qrate, const double *wb, 
  * j(t) = j(t - dt/2) + dt/2 tau; q(t + dt/2) = q + dt/2 qdot(q, omega(t)), normalised;
  * j(t + dt/2) = j(t - dt/2) + dt tau; q(t + dt) = q + dt qdot(q(t + dt/2), omega(t + dt/2)),
  * normalised.  energies[s][4] = U(t), K_trans(t) with v(t) the mean of the two half-step
- * velocities, K_rot(t) = 1/2 sum_k jb_k(t)^2 / I_k over I_k > 0, W(t).                        */
+ * velocities, K_rot(t) = 1/2 sum_k jb_k(t)^2 / I_k over I_k > 0, W(t).
+ * NVT (Sec. 2: the temperature is kept constant by velocity rescaling), when T_target > 0: after
+ * each step the new half-step velocities and angular momenta are multiplied by
+ * beta = sqrt(T_target / T(t)), T(t) = 2 (K_trans(t) + K_rot(t)) / f with k_B = 1 and
+ * f = 3 N + the rotational degrees of freedom (the number of nonzero principal moments of each
+ * rotating molecule); the energies row keeps K(t) before the rescaling.                      */
 int oracle_step(const om_model *m, const double *mass, const double *inertia, double *pos, double *vel, double *quat,
                 double *angmom, const int32_t *comp, int64_t N, const double *box, double dt, int64_t nsteps,
-                double *energies) {
+                double T_target, double *energies) {
   double *F = (double *)malloc(sizeof(double) * 3 * (size_t)N);
   double *T = (double *)malloc(sizeof(double) * 3 * (size_t)N);
   if (!F || !T) {
@@ -518,6 +523,21 @@ int oracle_step(const om_model *m, const double *mass, const double *inertia, do
       energies[4 * step + 1] = Kt;
       energies[4 * step + 2] = Kr;
       energies[4 * step + 3] = glob[1];
+    }
+    if (T_target > 0.0) {
+      double f = 3.0 * (double)N;
+      for (int64_t i = 0; i < N; ++i) {
+        const double *I = inertia + 3 * comp[i];
+        if (quat && angmom) f += (I[0] > 0.0) + (I[1] > 0.0) + (I[2] > 0.0);
+      }
+      const double K = Kt + Kr;
+      const double beta = K > 0.0 ? sqrt(0.5 * f * T_target / K) : 1.0;
+      for (int64_t i = 0; i < N; ++i) {
+        for (int k = 0; k < 3; ++k) vel[3 * i + k] *= beta;
+        const double *I = inertia + 3 * comp[i];
+        if (quat && angmom && (I[0] > 0.0 || I[1] > 0.0 || I[2] > 0.0))
+          for (int k = 0; k < 3; ++k) angmom[3 * i + k] *= beta;
+      }
     }
   }
   free(F);

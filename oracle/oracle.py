@@ -69,7 +69,7 @@ def lib():
         L.oracle_all.argtypes = [mp, dp, dp, ip, ctypes.c_int64, dp, dp, dp, dp, dp, dp, lp]
         L.oracle_all.restype = ctypes.c_int
         L.oracle_step.argtypes = [mp, dp, dp, dp, dp, dp, dp, ip, ctypes.c_int64, dp, ctypes.c_double,
-                                  ctypes.c_int64, dp]
+                                  ctypes.c_int64, ctypes.c_double, dp]
         L.oracle_step.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
@@ -196,8 +196,9 @@ def forces(model, pos, quat, comp, box):
     return dict(F=F, T=T, u=u, w=w, U=glob[0], W=glob[1], Wd=glob[2:5].copy(), npairs=int(npairs[0]))
 
 
-def step(model, pos, vel, quat, angmom, comp, box, dt, nsteps):
-    """Leapfrog nsteps on copies of the state.  Returns (pos, vel, quat, angmom, energies[n,4])."""
+def step(model, pos, vel, quat, angmom, comp, box, dt, nsteps, T_target=0.0):
+    """Leapfrog nsteps on copies of the state (with velocity rescaling to the kinetic temperature
+    T_target after each step when T_target > 0).  Returns (pos, vel, quat, angmom, energies[n,4])."""
     om, pos, quat, comp, N = _system(model, pos, quat, comp)
     pos = pos.copy()
     vel = _f64(vel, (N, 3)).copy()
@@ -205,10 +206,48 @@ def step(model, pos, vel, quat, angmom, comp, box, dt, nsteps):
     angmom = None if angmom is None else _f64(angmom, (N, 3)).copy()
     en = np.zeros((nsteps, 4))
     rc = lib().oracle_step(ctypes.byref(om.struct), _dp(om.mass), _dp(om.inertia), _dp(pos), _dp(vel), _dp(quat),
-                           _dp(angmom), _ip(comp), N, _dp(_f64(box, 3)), float(dt), int(nsteps), _dp(en))
+                           _dp(angmom), _ip(comp), N, _dp(_f64(box, 3)), float(dt), int(nsteps), float(T_target),
+                           _dp(en))
     if rc != 0:
         raise RuntimeError(f"oracle_step failed ({rc})")
     return pos, vel, quat, angmom, en
+
+
+def long_range_correction(model, counts, box):
+    """Isotropic cut-off corrections of energy and virial (Sec. 3: the long-range part of the
+    dispersive interaction is approximated by a mean-field integral beyond r_c).  Reading: every
+    pair of LJ sites (a of component A, b of component B) contributes the tail of the full
+    LJ 12-6 potential beyond r_c as if the sites sat at the molecular centres (the cutoff acts on
+    the centre distance), with a uniform pair density N_A N_B / V:
+        U_lrc = sum_{A,B} sum_{a,b} 2 pi N_A N_B / V * int_rc^inf r^2 u_ab(r) dr
+              = sum 2 pi N_A N_B / V * 4 eps_ab (sigma_ab^12 / (9 rc^9) - sigma_ab^6 / (3 rc^3)),
+        W_lrc = sum 2 pi N_A N_B / V * int_rc^inf r^2 (-r u_ab'(r)) dr
+              = sum 2 pi N_A N_B / V * 4 eps_ab (4 sigma_ab^12 / (3 rc^9) - 2 sigma_ab^6 / rc^3),
+    (A, B ordered, so each unlike pair of components enters twice and N_A N_B / 2 pairs of like
+    ones once), eps_ab = xi_AB sqrt(eps_a eps_b), sigma_ab = eta_AB (sigma_a + sigma_b) / 2.  The
+    truncated and shifted potential (lj_shift) is the model itself: no correction.  The reaction
+    field already accounts for the dipolar far field; charges and quadrupoles get none.
+    Returns (U_lrc, W_lrc)."""
+    if model.get("lj_shift", False):
+        return 0.0, 0.0
+    comps = model["components"]
+    nc = len(comps)
+    xi = np.ones((nc, nc)) if model.get("xi") is None else np.asarray(model["xi"], dtype=np.float64)
+    eta = np.ones((nc, nc)) if model.get("eta") is None else np.asarray(model["eta"], dtype=np.float64)
+    rc = float(model["rc"])
+    V = float(np.prod(np.asarray(box, dtype=np.float64)))
+    U = W = 0.0
+    for A in range(nc):
+        for B in range(nc):
+            dens = 2.0 * math.pi * float(counts[A]) * float(counts[B]) / V
+            for sa in [s for s in comps[A]["sites"] if s["kind"] == "lj"]:
+                for sb in [s for s in comps[B]["sites"] if s["kind"] == "lj"]:
+                    eps = xi[A, B] * math.sqrt(sa["eps"] * sb["eps"])
+                    sig = eta[A, B] * 0.5 * (sa["sigma"] + sb["sigma"])
+                    s3 = sig ** 3 / rc ** 3
+                    U += dens * 4.0 * eps * sig ** 3 * (s3 ** 3 / 9.0 - s3 / 3.0)
+                    W += dens * 4.0 * eps * sig ** 3 * (4.0 * s3 ** 3 / 3.0 - 2.0 * s3)
+    return U, W
 
 
 def num_threads() -> int:

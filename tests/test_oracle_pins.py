@@ -408,3 +408,91 @@ def test_free_rotor(oracle):
         ks.append(np.abs(en[:, 2] - en[0, 2]).max() / en[0, 2])
     assert ks[1] < 1e-4
     assert ks[0] / ks[1] > 3.0  # at least second order (observed ~8: third order for a free top)
+
+
+# ----------------------------------------------------------------------------- NVT, cut-off corrections
+
+def _quad_tail(eps, sig, rc, power_weight):
+    """int_rc^inf r^2 u(r) dr (power_weight = 0) or int_rc^inf r^2 (-r u'(r)) dr (= 1), by
+    adaptive quadrature of the LJ 12-6 potential written out here."""
+    from scipy.integrate import quad
+    u = lambda r: 4.0 * eps * ((sig / r) ** 12 - (sig / r) ** 6)
+    mru = lambda r: 4.0 * eps * (12.0 * (sig / r) ** 12 - 6.0 * (sig / r) ** 6)  # -r u'(r)
+    f = (lambda r: r * r * u(r)) if power_weight == 0 else (lambda r: r * r * mru(r))
+    val, err = quad(f, rc, np.inf, epsabs=0.0, epsrel=1e-13, limit=200)
+    return val
+
+
+@pytest.mark.parametrize("case", ["lj", "mixture_xi_eta", "2clj"])
+def test_long_range_correction_matches_quadrature(oracle, case):
+    """Cut-off corrections (Sec. 3: mean-field integral of the dispersive tail) against adaptive
+    quadrature of the pair integral 2 pi N_A N_B / V int_rc^inf r^2 u(r) dr per LJ site pair, with
+    Lorentz-Berthelot mixing and binary factors; the textbook single-component value
+    U/N = 8/3 pi rho eps sigma^3 [(sigma/rc)^9 / 3 - (sigma/rc)^3] is checked as well."""
+    box = np.array([11.0, 12.0, 13.0])
+    V = float(np.prod(box))
+    rc = 3.0
+    if case == "lj":
+        m = dict(W.lj_model(rc, shift=False))
+        counts = [1500]
+    elif case == "mixture_xi_eta":
+        m = W.mixture_model(rc=rc)
+        m = dict(m, lj_shift=False, xi=[[1.0, 0.93], [0.93, 1.0]], eta=[[1.0, 1.07], [1.07, 1.0]])
+        counts = [700, 900]
+    else:
+        m = dict(W.twoclj_q_model(rc=rc), lj_shift=False)
+        counts = [1200]
+    U, Wv = oracle.long_range_correction(m, counts, box)
+    comps = m["components"]
+    nc = len(comps)
+    xi = np.ones((nc, nc)) if m.get("xi") is None else np.asarray(m["xi"])
+    eta = np.ones((nc, nc)) if m.get("eta") is None else np.asarray(m["eta"])
+    Uq = Wq = 0.0
+    for A in range(nc):
+        for B in range(nc):
+            for sa in [s for s in comps[A]["sites"] if s["kind"] == "lj"]:
+                for sb in [s for s in comps[B]["sites"] if s["kind"] == "lj"]:
+                    eps = xi[A, B] * math.sqrt(sa["eps"] * sb["eps"])
+                    sig = eta[A, B] * 0.5 * (sa["sigma"] + sb["sigma"])
+                    pref = 2.0 * math.pi * counts[A] * counts[B] / V
+                    Uq += pref * _quad_tail(eps, sig, rc, 0)
+                    Wq += pref * _quad_tail(eps, sig, rc, 1)
+    assert U == pytest.approx(Uq, rel=1e-11)
+    assert Wv == pytest.approx(Wq, rel=1e-11)
+    if case == "lj":
+        rho = counts[0] / V
+        x = 1.0 / rc
+        assert U / counts[0] == pytest.approx(8.0 / 3.0 * math.pi * rho * (x ** 9 / 3.0 - x ** 3), rel=1e-13)
+    assert oracle.long_range_correction(dict(m, lj_shift=True), counts, box) == (0.0, 0.0)
+
+
+@pytest.mark.parametrize("kind", ["ljts", "2cljq"])
+def test_velocity_rescaling_thermostat(oracle, kind):
+    """NVT by velocity rescaling (Sec. 2): one step with the thermostat equals one step without it
+    followed by v <- beta v, j <- beta j with beta = sqrt(T_target / T(t)), where the test forms
+    T(t) = 2 K(t) / f itself (k_B = 1; f = 3N + 2 per linear molecule, the 2CLJQ has I_z = 0)."""
+    if kind == "ljts":
+        c = W.random_gas(300, [9.0, 9.0, 9.0], W.lj_model(2.5), seed=5, dmin=0.9)
+        m, pos, quat, comp, box = c["model"], c["pos"], None, None, c["box"]
+        vel = W.maxwell_velocities(np.random.default_rng(3), np.ones(300), 1.3)
+        angmom = None
+        f = 3 * 300
+    else:
+        m = W.twoclj_q_model(rc=4.0)
+        c = W.random_gas(120, [12.5, 12.5, 12.5], m, seed=6, dmin=1.3)
+        pos, box = c["pos"], c["box"]
+        rng = np.random.default_rng(8)
+        quat = W.random_quaternions(rng, 120)
+        comp = np.zeros(120, dtype=np.int32)
+        vel = W.maxwell_velocities(rng, np.full(120, m["components"][0]["mass"]), 1.3)
+        angmom = W.angular_momenta(rng, quat, m["components"][0]["inertia"], 1.3)
+        f = 3 * 120 + 2 * 120
+    T_target = 0.8
+    _, v0, _, j0, e0 = oracle.step(m, pos, vel, quat, angmom, comp, box, 0.002, 1)
+    p1, v1, q1, j1, e1 = oracle.step(m, pos, vel, quat, angmom, comp, box, 0.002, 1, T_target=T_target)
+    np.testing.assert_array_equal(e0, e1)  # the energies row keeps K(t) before the rescaling
+    K = e0[0, 1] + e0[0, 2]
+    beta = math.sqrt(T_target / (2.0 * K / f))
+    np.testing.assert_allclose(v1, beta * v0, rtol=1e-14, atol=0)
+    if angmom is not None:
+        np.testing.assert_allclose(j1, beta * j0, rtol=1e-14, atol=0)
