@@ -178,6 +178,34 @@ int md_step(md_model *m, md_cells *cells, double *pos, double *vel, double *quat
             const int32_t *comp, int64_t N, const double box[3], double dt, int64_t nsteps, int precision,
             double *energies, void *stream);
 
+/* NVT by velocity rescaling (Sec. 2: in NVT the temperature is kept constant by velocity
+ * rescaling), applied by later md_step calls on this model (host call, no device work):
+ *   T_target > 0  every step ends by multiplying the new half-step velocities v(t + dt/2) and,
+ *                 for molecules with inertia, the angular momenta j(t + dt/2) by
+ *                 beta = sqrt(T_target / T(t)),  T(t) = 2 (K_trans(t) + K_rot(t)) / f  (k_B = 1),
+ *                 f = 3 N + the number of nonzero principal moments of every molecule with
+ *                 inertia; K(t) as in the energies row, which keeps the values before rescaling
+ *                 (beta = 1 when K(t) = 0);
+ *   T_target = 0  NVE (the default).
+ * Errors: NULL model or T_target < 0 (MD_EINVAL), T_target not finite (MD_ENONFINITE). */
+int md_set_thermostat(md_model *m, double T_target);
+
+/* Isotropic cut-off corrections of the potential energy and of the virial W = sum r_ij . F_ij
+ * (Sec. 3: the long-range part of the dispersive interaction is a mean-field integral beyond
+ * r_c).  Host-only: takes the component table as md_model_create does (host memory) and returns
+ *   *u_lrc = sum_{A,B} sum_{a,b} 2 pi N_A N_B / V * 4 eps_ab (sigma_ab^12 / (9 r_c^9) - sigma_ab^6 / (3 r_c^3))
+ *   *w_lrc = sum_{A,B} sum_{a,b} 2 pi N_A N_B / V * 4 eps_ab (4 sigma_ab^12 / (3 r_c^9) - 2 sigma_ab^6 / r_c^3)
+ * over ordered component pairs (A, B) and their LJ sites (a, b), Lorentz-Berthelot mixing with
+ * xi/eta, each site pair taken at the centre distance (the cutoff acts on the COM distance),
+ * V = box[0] box[1] box[2], counts [ncomp] (host, >= 0) molecules per component.  With
+ * MD_LJ_SHIFT in flags the truncated-shifted potential is the model and both are 0.  Charges,
+ * dipoles (reaction field) and quadrupoles add nothing.
+ * Errors: NULL argument or invalid table / count / box / r_c (MD_EINVAL, MD_ECOMP,
+ * MD_ENONFINITE, as md_model_create). */
+int md_long_range_correction(const md_component_desc *comps, int32_t ncomp, const double *xi, const double *eta,
+                             double rc, uint32_t flags, const int64_t *counts, const double box[3], double *u_lrc,
+                             double *w_lrc);
+
 /* Gradient of gU * U for the built configuration, recomputing every pair (no stored pair list):
  *   dpos    [N][3]  gU dU/dr_i (= -gU F_i)
  *   dquat   [N][4]  gU dU/dq_i with respect to the raw quaternion components (NULL allowed)

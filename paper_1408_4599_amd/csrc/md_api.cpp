@@ -393,7 +393,7 @@ static int forces_impl(md_model *m, const md_cells *c, int precision, double *fo
   const int64_t nb = pair_blocks(c->ncell);
   int rc;
   if ((rc = grow(m->partial, m->cap_partial,
-                 nb * PARTIAL_COLS + 2 * ((3 * c->N + 255) / 256 + (c->N + 255) / 256), "partial")))
+                 nb * PARTIAL_COLS + KIN_COLS * ((3 * c->N + 255) / 256 + (c->N + 255) / 256), "partial")))
     return rc;
   PairOut o{force, torque, u_mol, w_mol, nnb_mol, m->partial};
   int64_t nblocks = 0;
@@ -449,12 +449,81 @@ int md_step(md_model *m, md_cells *c, double *pos, double *vel, double *quat, do
     rc = launch_leapfrog(m, pos, vel, quat, angmom, m->host.ncomp > 1 ? comp : nullptr, N, box, dt, m->force,
                          m->torque, kin, &nkin, s);
     // energies row: U, W from the pair partials and K_trans, K_rot from the leapfrog's, in one
-    // reduction (skipped when no energies are asked for)
-    if (!rc && erow) rc = launch_reduce_forces(m, nbp, m->partial, m->uw + 8, nullptr, erow, s, kin, nkin);
+    // reduction (skipped when neither energies nor the thermostat need it); the thermostat then
+    // rescales the new half-step velocities from the reduced K(t) and degrees of freedom
+    const bool nvt = m->T_target > 0.0;
+    if (!rc && (erow || nvt)) rc = launch_reduce_forces(m, nbp, m->partial, m->uw + 8, nullptr, erow, s, kin, nkin);
+    if (!rc && nvt)
+      rc = launch_rescale(m, vel, angmom, m->host.ncomp > 1 ? comp : nullptr, N, m->uw + 13, m->T_target, s);
     prof_end(m, PROF_STEP, s, ev);
     if (rc) return rc;
   }
   return sync_check(m, s);
+}
+
+int md_set_thermostat(md_model *m, double T_target) {
+  if (!m) return set_error(MD_EINVAL, "md_set_thermostat: NULL model");
+  if (!std::isfinite(T_target)) return set_error(MD_ENONFINITE, "md_set_thermostat: T_target not finite");
+  if (T_target < 0.0) return set_error(MD_EINVAL, "md_set_thermostat: T_target < 0");
+  m->T_target = T_target;
+  return MD_OK;
+}
+
+int md_long_range_correction(const md_component_desc *comps, int32_t ncomp, const double *xi, const double *eta,
+                             double rc, uint32_t flags, const int64_t *counts, const double box[3], double *u_lrc,
+                             double *w_lrc) {
+  if (!comps || !counts || !box || !u_lrc || !w_lrc)
+    return set_error(MD_EINVAL, "md_long_range_correction: NULL argument");
+  if (ncomp < 1) return set_error(MD_EINVAL, "md_long_range_correction: ncomp < 1");
+  if (ncomp > MD_MAX_COMP) return set_error(MD_ECOMP, "md_long_range_correction: ncomp exceeds MD_MAX_COMP");
+  if (!std::isfinite(rc)) return set_error(MD_ENONFINITE, "md_long_range_correction: r_c not finite");
+  if (!(rc > 0.0)) return set_error(MD_EINVAL, "md_long_range_correction: r_c <= 0");
+  if (flags & ~(MD_LJ_SHIFT | MD_CHECK)) return set_error(MD_EINVAL, "md_long_range_correction: unknown flag");
+  double V = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    if (!std::isfinite(box[k])) return set_error(MD_ENONFINITE, "md_long_range_correction: box not finite");
+    if (!(box[k] > 0.0)) return set_error(MD_EINVAL, "md_long_range_correction: box <= 0");
+    V *= box[k];
+  }
+  for (int c = 0; c < ncomp; ++c) {
+    const md_component_desc &d = comps[c];
+    if (counts[c] < 0) return set_error(MD_EINVAL, "md_long_range_correction: negative count");
+    if (d.n_lj < 0) return set_error(MD_EINVAL, "md_long_range_correction: negative site count");
+    if (d.n_lj > MD_MAX_LJ) return set_error(MD_ECOMP, "md_long_range_correction: site count exceeds the compiled limits");
+    if (d.n_lj && (!d.lj_eps || !d.lj_sigma)) return set_error(MD_EINVAL, "md_long_range_correction: NULL site table");
+    for (int a = 0; a < d.n_lj; ++a) {
+      if (!std::isfinite(d.lj_eps[a]) || !std::isfinite(d.lj_sigma[a]))
+        return set_error(MD_ENONFINITE, "md_long_range_correction: non-finite site table entry");
+      if (!(d.lj_eps[a] > 0.0) || !(d.lj_sigma[a] > 0.0))
+        return set_error(MD_EINVAL, "md_long_range_correction: LJ epsilon and sigma must be > 0");
+    }
+  }
+  for (int a = 0; a < ncomp * ncomp; ++a) {
+    const double x = xi ? xi[a] : 1.0, e = eta ? eta[a] : 1.0;
+    if (!std::isfinite(x) || !std::isfinite(e)) return set_error(MD_ENONFINITE, "md_long_range_correction: xi/eta not finite");
+    if (!(x > 0.0) || !(e > 0.0)) return set_error(MD_EINVAL, "md_long_range_correction: xi/eta must be > 0");
+  }
+  double U = 0.0, W = 0.0;
+  if (!(flags & MD_LJ_SHIFT)) {
+    const double pi = 3.14159265358979323846;
+    for (int A = 0; A < ncomp; ++A)
+      for (int B = 0; B < ncomp; ++B) {
+        const double dens = 2.0 * pi * (double)counts[A] * (double)counts[B] / V;
+        const double x = xi ? xi[A * ncomp + B] : 1.0, e = eta ? eta[A * ncomp + B] : 1.0;
+        for (int a = 0; a < comps[A].n_lj; ++a)
+          for (int b = 0; b < comps[B].n_lj; ++b) {
+            const double eps = x * std::sqrt(comps[A].lj_eps[a] * comps[B].lj_eps[b]);
+            const double sig = e * 0.5 * (comps[A].lj_sigma[a] + comps[B].lj_sigma[b]);
+            const double s3 = sig * sig * sig / (rc * rc * rc);
+            const double e4s3 = 4.0 * eps * sig * sig * sig;
+            U += dens * e4s3 * (s3 * s3 * s3 / 9.0 - s3 / 3.0);
+            W += dens * e4s3 * (4.0 * s3 * s3 * s3 / 3.0 - 2.0 * s3);
+          }
+      }
+  }
+  *u_lrc = U;
+  *w_lrc = W;
+  return MD_OK;
 }
 
 int md_forces_adjoint(md_model *m, const md_cells *c, int precision, double gU, double *dpos, double *dquat,

@@ -114,9 +114,10 @@ struct md_model {
   double *red2 = nullptr;       // second-stage reduction buffer
   double *pgrad = nullptr;      // adjoint parameter partials
   int64_t cap_pgrad = 0;
-  // md_step scratch
+  // md_step scratch; uw[8..15]: U, W, W_xx, W_yy, W_zz, K_trans, K_rot, rotational dof of a step
   double *force = nullptr, *torque = nullptr, *uw = nullptr;
   int64_t cap_step = 0;
+  double T_target = 0.0;        // velocity-rescaling thermostat (0: NVE)
   // profiling
   bool profiling = false;
   struct Ev {
@@ -145,12 +146,17 @@ int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat
                  const double inv_h[3], const int32_t *order, hipStream_t s);
 int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o, hipStream_t s, int64_t *nblocks);
 int launch_reduce(md_model *m, int64_t nrows, int ncols, const double *rows, double *out, hipStream_t s);
-// pair partial rows -> U, W, W_aa, pair count, energies row; with kin_rows (the leapfrog's
-// [kin_nrows][2] kinetic-energy partials) also K_trans and K_rot of the energies row
+// pair partial rows -> uw[0..4] (U, W, W_aa), pair count, energies row; with kin_rows (the
+// leapfrog's [kin_nrows][KIN_COLS] partials) also K_trans and K_rot of the energies row and
+// uw[5..7] = K_trans, K_rot, rotational degrees of freedom
 int launch_reduce_forces(md_model *m, int64_t nrows, const double *rows, double *uw, int64_t *npairs,
                          double *energies_row, hipStream_t s, const double *kin_rows = nullptr,
                          int64_t kin_nrows = 0);
-// leapfrog step; writes its kinetic-energy partial rows ([*kin_nrows][2]) to kin_rows
+constexpr int KIN_COLS = 3;  // K_trans, K_rot, rotational degrees of freedom
+// velocity rescaling to the kinetic temperature T_target from the reduced kin[0..2]
+int launch_rescale(md_model *m, double *vel, double *angmom, const int32_t *comp, int64_t N, const double *kin,
+                   double T_target, hipStream_t s);
+// leapfrog step; writes its kinetic-energy partial rows ([*kin_nrows][KIN_COLS]) to kin_rows
 int launch_leapfrog(md_model *m, double *pos, double *vel, double *quat, double *angmom, const int32_t *comp,
                     int64_t N, const double box[3], double dt, const double *force, const double *torque,
                     double *kin_rows, int64_t *kin_nrows, hipStream_t s);

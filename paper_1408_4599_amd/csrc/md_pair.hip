@@ -861,7 +861,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double *red2
     uw[0] = U, uw[1] = W, uw[2] = res[1], uw[3] = res[2], uw[4] = res[3];
     if (npairs) *npairs = (int64_t)(res[4] * 0.5);
     if (erow) erow[0] = U, erow[3] = W;
-    if (erow && ncols == PARTIAL_COLS + 2) erow[1] = res[PARTIAL_COLS], erow[2] = res[PARTIAL_COLS + 1];
+    if (ncols == PARTIAL_COLS + KIN_COLS) {
+      if (erow) erow[1] = res[PARTIAL_COLS], erow[2] = res[PARTIAL_COLS + 1];
+      uw[5] = res[PARTIAL_COLS], uw[6] = res[PARTIAL_COLS + 1], uw[7] = res[PARTIAL_COLS + 2];
+    }
   } else {
     for (int col = 0; col < ncols; ++col) out[col] = res[col];
   }
@@ -936,7 +939,7 @@ int launch_reduce(md_model *m, int64_t nrows, int ncols, const double *rows, dou
 int launch_reduce_forces(md_model *m, int64_t nrows, const double *rows, double *uw, int64_t *npairs, double *erow,
                          hipStream_t s, const double *kin_rows, int64_t kin_nrows) {
   const int64_t chunk = (nrows + RED_BLOCKS - 1) / RED_BLOCKS;
-  const int kc = kin_rows ? 2 : 0;
+  const int kc = kin_rows ? KIN_COLS : 0;
   const int64_t chunk2 = (kin_nrows + RED_BLOCKS - 1) / RED_BLOCKS;
   k_reduce_cols<<<RED_BLOCKS, RED_THREADS, 0, s>>>(rows, nrows, PARTIAL_COLS, chunk > 0 ? chunk : 1, kin_rows,
                                                    kc ? kin_nrows : 0, kc, chunk2 > 0 ? chunk2 : 1, m->red2);

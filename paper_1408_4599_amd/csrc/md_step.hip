@@ -15,7 +15,7 @@ struct LeapArgs {
   double Lx, Ly, Lz, dt;
   const double *force, *torque;
   const ModelDev *md;
-  double *partial;  // [rows][2]: K_trans, K_rot block partials
+  double *partial;  // [rows][KIN_COLS]: K_trans, K_rot, rotational dof block partials
 };
 
 __device__ __forceinline__ void rotmat(const double *q, double A[3][3]) {
@@ -47,18 +47,27 @@ __device__ __forceinline__ void q_normalise(double *q) {
   q[0] /= n, q[1] /= n, q[2] /= n, q[3] /= n;
 }
 
-// Fixed-order block sum of one value (wave shuffles, then the four wave sums in order) into
-// partial[row][col]; the other column of the row is set to zero.
-__device__ __forceinline__ void block_partial(double v, double *partial, int64_t row, int col) {
-  __shared__ double sk[4];
+// Fixed-order block sums (wave shuffles, then the four wave sums in order) of the values of
+// columns col .. col + n - 1 into partial[row][...]; the other columns of the row are set to zero.
+template <int n>
+__device__ __forceinline__ void block_partial(const double (&v)[n], double *partial, int64_t row, int col) {
+  __shared__ double sk[n][4];
+  double x[n];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  for (int c = 0; c < n; ++c) {
+    x[c] = v[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x[c] += __shfl_xor(x[c], o);
+  }
   const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) sk[w] = v;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int c = 0; c < n; ++c) sk[c][w] = x[c];
   __syncthreads();
   if (threadIdx.x == 0) {
-    partial[2 * row + col] = ((sk[0] + sk[1]) + sk[2]) + sk[3];
-    partial[2 * row + 1 - col] = 0.0;
+    double *r = partial + KIN_COLS * row;
+    for (int c = 0; c < KIN_COLS; ++c) r[c] = 0.0;
+    for (int c = 0; c < n; ++c) r[col + c] = ((sk[c][0] + sk[c][1]) + sk[c][2]) + sk[c][3];
   }
 }
 
@@ -80,19 +89,21 @@ __global__ __launch_bounds__(256) void k_leapfrog_trans(LeapArgs a) {
     a.vel[t] = vnew;
     a.pos[t] = wrap1(a.pos[t] + a.dt * vnew, k == 0 ? a.Lx : (k == 1 ? a.Ly : a.Lz));
   }
-  block_partial(kt, a.partial, blockIdx.x, 0);
+  const double kv[1] = {kt};
+  block_partial(kv, a.partial, blockIdx.x, 0);
 }
 
 // Rotational leapfrog (Fincham), one thread per molecule; K_rot at the half step.  Block partials
 // go to rows row0 + blockIdx.x.
 __global__ __launch_bounds__(256) void k_leapfrog_rot(LeapArgs a, int64_t row0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double kr = 0.0;
+  double kr = 0.0, fr = 0.0;
   if (i < a.N) {
     int c = a.comp ? a.comp[i] : 0;
     if (c < 0 || c >= a.md->ncomp) c = 0;
     const CompDev &cd = a.md->comp[c];
     if (cd.rotates) {
+      fr = (double)((cd.inertia[0] > 0.0) + (cd.inertia[1] > 0.0) + (cd.inertia[2] > 0.0));
       double q[4], jm[3], tq[3];
 #pragma unroll
       for (int k = 0; k < 4; ++k) q[k] = a.quat[4 * i + k];
@@ -117,7 +128,27 @@ __global__ __launch_bounds__(256) void k_leapfrog_rot(LeapArgs a, int64_t row0) 
       for (int k = 0; k < 3; ++k) a.angmom[3 * i + k] = jn[k];
     }
   }
-  block_partial(kr, a.partial, row0 + blockIdx.x, 1);
+  const double kv[2] = {kr, fr};
+  block_partial(kv, a.partial, row0 + blockIdx.x, 1);
+}
+
+// Velocity rescaling (NVT): v *= beta for every component, j *= beta for molecules with inertia,
+// beta = sqrt(f T_target / (2 K)), f = 3 N + kin[2], K = kin[0] + kin[1] (beta = 1 if K = 0).
+// One thread per Cartesian component.
+__global__ __launch_bounds__(256) void k_rescale(double *vel, double *angmom, const int32_t *comp,
+                                                 const ModelDev *md, int64_t N, const double *kin,
+                                                 double T_target) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * N) return;
+  const double K = kin[0] + kin[1];
+  const double f = 3.0 * (double)N + kin[2];
+  const double beta = K > 0.0 ? sqrt(0.5 * f * T_target / K) : 1.0;
+  vel[t] *= beta;
+  if (angmom) {
+    int c = comp ? comp[t / 3] : 0;
+    if (c < 0 || c >= md->ncomp) c = 0;
+    if (md->comp[c].rotates) angmom[t] *= beta;
+  }
 }
 
 }  // namespace
@@ -134,6 +165,14 @@ int launch_leapfrog(md_model *m, double *pos, double *vel, double *quat, double 
   if (rot) k_leapfrog_rot<<<(unsigned)nr, 256, 0, s>>>(a, nt);
   *kin_nrows = nt + nr;
   return check_hip(hipGetLastError(), "k_leapfrog");
+}
+
+int launch_rescale(md_model *m, double *vel, double *angmom, const int32_t *comp, int64_t N, const double *kin,
+                   double T_target, hipStream_t s) {
+  const bool rot = !m->single_site && angmom;
+  k_rescale<<<(unsigned)((3 * N + 255) / 256), 256, 0, s>>>(vel, rot ? angmom : nullptr, comp, m->dev, N, kin,
+                                                            T_target);
+  return check_hip(hipGetLastError(), "k_rescale");
 }
 
 }  // namespace mdcell

@@ -77,9 +77,12 @@ def lib():
     L.md_status.argtypes = [vp, _ip]
     L.md_profile.argtypes = [vp, ctypes.c_int]
     L.md_profile_read.argtypes = [vp, ctypes.c_char_p, _dp, _lp]
+    L.md_set_thermostat.argtypes = [vp, ctypes.c_double]
+    L.md_long_range_correction.argtypes = [ctypes.POINTER(ComponentDesc), ctypes.c_int32, _dp, _dp, ctypes.c_double,
+                                           ctypes.c_uint32, _lp, _dp, _dp, _dp]
     for name in ("md_model_create", "md_model_destroy", "md_cells_create", "md_cells_destroy", "md_cells_view",
                  "md_build_cells", "md_forces", "md_step", "md_forces_adjoint", "md_status", "md_profile",
-                 "md_profile_read"):
+                 "md_profile_read", "md_set_thermostat", "md_long_range_correction"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -115,6 +118,59 @@ def _arr(x, n=None):
     return a
 
 
+def _component_descs(model: dict):
+    """md_component_desc array (host) for a model dictionary, and the arrays it points into."""
+    comps = model["components"]
+    nc = len(comps)
+    descs = (ComponentDesc * nc)()
+    keep = []
+    for d, comp in zip(descs, comps):
+        by = {k: [s for s in comp["sites"] if s["kind"] == k] for k in ("lj", "charge", "dipole", "quadrupole")}
+        d.n_lj, d.n_chg, d.n_dip, d.n_quad = (len(by[k]) for k in ("lj", "charge", "dipole", "quadrupole"))
+
+        def put(vals):
+            a = _arr(vals) if len(vals) else np.zeros(1)
+            keep.append(a)
+            return a.ctypes.data_as(_dp)
+
+        d.lj_pos = put([s["pos"] for s in by["lj"]])
+        d.lj_eps = put([s["eps"] for s in by["lj"]])
+        d.lj_sigma = put([s["sigma"] for s in by["lj"]])
+        d.chg_pos = put([s["pos"] for s in by["charge"]])
+        d.chg_q = put([s["q"] for s in by["charge"]])
+        d.dip_pos = put([s["pos"] for s in by["dipole"]])
+        d.dip_dir = put([s["dir"] for s in by["dipole"]])
+        d.dip_mu = put([s["mu"] for s in by["dipole"]])
+        d.quad_pos = put([s["pos"] for s in by["quadrupole"]])
+        d.quad_dir = put([s["dir"] for s in by["quadrupole"]])
+        d.quad_Q = put([s["Q"] for s in by["quadrupole"]])
+        d.mass = float(comp["mass"])
+        for k in range(3):
+            d.inertia[k] = float(comp["inertia"][k])
+    xi = None if model.get("xi") is None else _arr(model["xi"])
+    eta = None if model.get("eta") is None else _arr(model["eta"])
+    keep += [xi, eta]
+    return descs, keep, xi, eta
+
+
+def long_range_correction(model: dict, counts, box):
+    """(U_lrc, W_lrc): isotropic cut-off corrections of energy and virial (md_long_range_correction;
+    host only, no device needed).  counts: molecules per component."""
+    descs, keep, xi, eta = _component_descs(model)
+    cnt = np.ascontiguousarray(np.asarray(counts, dtype=np.int64).reshape(-1))
+    if cnt.shape[0] != len(model["components"]):
+        raise ValueError("counts must have one entry per component")
+    b = _arr(box)
+    u, w = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    flags = MD_LJ_SHIFT if model.get("lj_shift") else 0
+    _check(lib().md_long_range_correction(descs, len(model["components"]),
+                                          None if xi is None else xi.ctypes.data_as(_dp),
+                                          None if eta is None else eta.ctypes.data_as(_dp), float(model["rc"]), flags,
+                                          cnt.ctypes.data_as(_lp), b.ctypes.data_as(_dp), ctypes.byref(u),
+                                          ctypes.byref(w)))
+    return u.value, w.value
+
+
 class Model:
     """A molecule model (component site tables, mixing, cutoff, reaction field) on the device.
     Built from the model dictionaries of ``workloads``."""
@@ -122,33 +178,7 @@ class Model:
     def __init__(self, model: dict, check: bool = False):
         comps = model["components"]
         nc = len(comps)
-        descs = (ComponentDesc * nc)()
-        self._keep = []
-        for d, comp in zip(descs, comps):
-            by = {k: [s for s in comp["sites"] if s["kind"] == k] for k in ("lj", "charge", "dipole", "quadrupole")}
-            d.n_lj, d.n_chg, d.n_dip, d.n_quad = (len(by[k]) for k in ("lj", "charge", "dipole", "quadrupole"))
-
-            def put(vals):
-                a = _arr(vals) if len(vals) else np.zeros(1)
-                self._keep.append(a)
-                return a.ctypes.data_as(_dp)
-
-            d.lj_pos = put([s["pos"] for s in by["lj"]])
-            d.lj_eps = put([s["eps"] for s in by["lj"]])
-            d.lj_sigma = put([s["sigma"] for s in by["lj"]])
-            d.chg_pos = put([s["pos"] for s in by["charge"]])
-            d.chg_q = put([s["q"] for s in by["charge"]])
-            d.dip_pos = put([s["pos"] for s in by["dipole"]])
-            d.dip_dir = put([s["dir"] for s in by["dipole"]])
-            d.dip_mu = put([s["mu"] for s in by["dipole"]])
-            d.quad_pos = put([s["pos"] for s in by["quadrupole"]])
-            d.quad_dir = put([s["dir"] for s in by["quadrupole"]])
-            d.quad_Q = put([s["Q"] for s in by["quadrupole"]])
-            d.mass = float(comp["mass"])
-            for k in range(3):
-                d.inertia[k] = float(comp["inertia"][k])
-        xi = None if model.get("xi") is None else _arr(model["xi"])
-        eta = None if model.get("eta") is None else _arr(model["eta"])
+        descs, self._keep, xi, eta = _component_descs(model)
         flags = (MD_LJ_SHIFT if model.get("lj_shift") else 0) | (MD_CHECK if check else 0)
         h = ctypes.c_void_p()
         _check(lib().md_model_create(descs, nc, None if xi is None else xi.ctypes.data_as(_dp),
@@ -176,6 +206,11 @@ class Model:
         v = ctypes.c_int32(0)
         _check(lib().md_status(self.handle, ctypes.byref(v)))
         return int(v.value)
+
+    def set_thermostat(self, T_target: float):
+        """NVT by velocity rescaling to the kinetic temperature T_target in later md_step calls
+        (0: NVE); md_set_thermostat."""
+        _check(lib().md_set_thermostat(self.handle, float(T_target)))
 
     def profile(self, enable: bool):
         _check(lib().md_profile(self.handle, int(enable)))

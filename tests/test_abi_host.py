@@ -112,3 +112,40 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(md, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         md.lib()
+
+
+@pytest.mark.parametrize("case", ["lj", "ljts", "mixture_xi_eta", "2cljq"])
+def test_long_range_correction_matches_oracle(L, oracle, case):
+    """md_long_range_correction (host only) against the oracle's cut-off corrections."""
+    from paper_1408_4599_amd import md, workloads as W
+    box = [11.0, 12.0, 13.0]
+    if case in ("lj", "ljts"):
+        m, counts = W.lj_model(3.0, shift=case == "ljts"), [1500]
+    elif case == "mixture_xi_eta":
+        m = dict(W.mixture_model(rc=3.0), lj_shift=False, xi=[[1.0, 0.93], [0.93, 1.0]], eta=[[1.0, 1.07], [1.07, 1.0]])
+        counts = [700, 900]
+    else:
+        m, counts = dict(W.twoclj_q_model(rc=3.0), lj_shift=False), [1200]
+    u, w = md.long_range_correction(m, counts, box)
+    uo, wo = oracle.long_range_correction(m, counts, box)
+    assert u == pytest.approx(uo, rel=1e-14, abs=0.0)
+    assert w == pytest.approx(wo, rel=1e-14, abs=0.0)
+    if case == "ljts":
+        assert (u, w) == (0.0, 0.0)
+
+
+@pytest.mark.parametrize("case,code", [("null_out", -1), ("rc_neg", -1), ("box_nan", -4), ("count_neg", -1),
+                                       ("ncomp_big", -3), ("eps_zero", -1)])
+def test_long_range_correction_rejects(L, case, code):
+    d, keep = _desc(eps=0.0 if case == "eps_zero" else 1.0)
+    counts = (ctypes.c_int64 * 1)(-5 if case == "count_neg" else 100)
+    box = (ctypes.c_double * 3)(float("nan") if case == "box_nan" else 10.0, 10.0, 10.0)
+    u, w = ctypes.c_double(), ctypes.c_double()
+    rc = L.md_long_range_correction(d, 5 if case == "ncomp_big" else 1, None, None, -1.0 if case == "rc_neg" else 2.5, 0,
+                                    counts, box, None if case == "null_out" else ctypes.byref(u), ctypes.byref(w))
+    assert rc == code
+    assert L.md_last_error()
+
+
+def test_set_thermostat_rejects(L):
+    assert L.md_set_thermostat(None, 1.0) == -1

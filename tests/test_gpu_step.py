@@ -21,8 +21,10 @@ def md():
     return _md
 
 
-def _run_gpu(md, cfg, nsteps, precision="fp64", dt=None):
+def _run_gpu(md, cfg, nsteps, precision="fp64", dt=None, T_target=0.0):
     m = md.Model(cfg["model"])
+    if T_target:
+        m.set_thermostat(T_target)
     cells = md.Cells()
     pos, vel = dev(cfg["pos"]), dev(cfg["vel"])
     quat, ang = dev(cfg["quat"]), dev(cfg["angmom"])
@@ -52,6 +54,31 @@ def test_step_fp64_matches_oracle_trajectory(md, oracle, name, nsteps, tol):
         assert np.abs(j - j_ref).max() < 1e3 * tol
     # U, K_trans, K_rot, W per step
     np.testing.assert_allclose(e, e_ref, rtol=1e-9, atol=1e-9 * np.abs(e_ref).max())
+
+
+@pytest.mark.parametrize("name,nsteps,tol", [("c1_ljts_4000", 50, 1e-9), ("c4_small", 20, 1e-9),
+                                             ("mixture_small", 20, 1e-9)])
+def test_step_nvt_matches_oracle_trajectory(md, oracle, name, nsteps, tol):
+    """NVT by velocity rescaling (md_set_thermostat): the trajectory and energies of the oracle's
+    rescaled leapfrog, with a target temperature away from the start state's; the kinetic
+    temperature must approach the target."""
+    cfg = W.make(name)
+    T_target = 0.7
+    p_ref, v_ref, q_ref, j_ref, e_ref = oracle.step(cfg["model"], cfg["pos"], cfg["vel"], cfg["quat"], cfg["angmom"],
+                                                    cfg["comp"], cfg["box"], cfg["dt"], nsteps, T_target=T_target)
+    p, v, q, j, e = _run_gpu(md, cfg, nsteps, T_target=T_target)
+    assert np.abs(_min_image(p - p_ref, cfg["box"])).max() < tol
+    assert np.abs(v - v_ref).max() < 1e3 * tol
+    if q is not None:
+        assert np.abs(q - q_ref).max() < 1e3 * tol
+        assert np.abs(j - j_ref).max() < 1e3 * tol
+    np.testing.assert_allclose(e, e_ref, rtol=1e-9, atol=1e-9 * np.abs(e_ref).max())
+    N = cfg["pos"].shape[0]
+    comps = cfg["model"]["components"]
+    comp = np.zeros(N, dtype=np.int64) if cfg["comp"] is None else cfg["comp"]
+    f = 3 * N + (0 if cfg["quat"] is None else sum(int(np.sum(np.asarray(comps[c]["inertia"]) > 0)) for c in comp))
+    T = 2.0 * (e[:, 1] + e[:, 2]) / f
+    assert abs(T[-1] - T_target) < abs(T[0] - T_target)
 
 
 def test_step_nve_fp32_energy_conservation(md):
