@@ -288,20 +288,21 @@ def main():
     f64_wall, f64_pair = (None, None) if args.no_fp64 else time_forces("fp64", args.force_evals)
 
     # ---- full steps ----
-    def run_steps(prec):
+    def run_steps(prec, nsteps=None):
+        nsteps = args.steps if nsteps is None else nsteps
         pos = dev(cfg["pos"])
         vel = dev(cfg["vel"])
         quat = dev(cfg["quat"])
         ang = dev(cfg["angmom"])
-        en = torch.empty((max(args.steps, args.warmup, 1), 4), dtype=torch.float64, device="cuda")
+        en = torch.empty((max(nsteps, args.warmup, 1), 4), dtype=torch.float64, device="cuda")
         if args.warmup:
             md.step(model, cells, pos, vel, quat, ang, comp_t, cfg["box"], cfg["dt"], args.warmup, prec, en)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        md.step(model, cells, pos, vel, quat, ang, comp_t, cfg["box"], cfg["dt"], args.steps, prec, en)
+        md.step(model, cells, pos, vel, quat, ang, comp_t, cfg["box"], cfg["dt"], nsteps, prec, en)
         torch.cuda.synchronize()
         dt_ = time.perf_counter() - t
-        e = en[:args.steps].cpu().numpy()
+        e = en[:nsteps].cpu().numpy()
         return dt_, e
 
     t32, e32 = run_steps("fp32")
@@ -310,6 +311,17 @@ def main():
     if not args.no_fp64:
         t64, e64 = run_steps("fp64")
         print(f"[bench] fp64 steps: {args.steps} in {t64:.3f}s", file=sys.stderr, flush=True)
+
+    # NVT: the same steps with velocity rescaling to the workload temperature (extra kernel and
+    # the kinetic reduction every step)
+    n_nvt = max(1, args.steps // 4)
+    model.set_thermostat(cfg["T"])
+    tnvt, envt = run_steps("fp32", n_nvt)
+    model.set_thermostat(0.0)
+    f_dof = 3 * N + (0 if cfg["quat"] is None else
+                     sum(int(np.sum(np.asarray(cfg["model"]["components"][c]["inertia"]) > 0))
+                         for c in (np.zeros(N, dtype=np.int64) if cfg["comp"] is None else cfg["comp"])))
+    print(f"[bench] fp32 NVT steps: {n_nvt} in {tnvt:.3f}s", file=sys.stderr, flush=True)
 
     ms_per_step = 1e3 * t32 / args.steps
     value = P * args.steps / t32
@@ -339,6 +351,8 @@ def main():
                         "fp32_pair_kernel_ms": 1e3 * f32_pair},
         "errors": errors,
         "nve_rel_energy_spread_fp32": float(np.abs(E - E[0]).max() / abs(E[0])),
+        "nvt_fp32": {"steps": n_nvt, "steps_per_s": n_nvt / tnvt, "ms_per_step": 1e3 * tnvt / n_nvt,
+                     "T_target": cfg["T"], "T_kin_last_step": float(2.0 * (envt[-1, 1] + envt[-1, 2]) / f_dof)},
         "roofline": {"bound": "alu", "achieved": W_alg / f32_pair / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": W_alg / f32_pair / PEAK_FP32,
                      "traffic": traffic,
