@@ -704,13 +704,25 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (act) {
-          int H = 0;
-          for (int s2 = 0; s2 < NS; ++s2) H += scnt[il + s2 * hc];
-          const int q0 = H * sl / NS, q1 = H * (sl + 1) / NS;
-          int sp = 0, j = q0, csp = scnt[il];
-          for (int q = q0; q < q1; ++q, ++j) {
-            while (j >= csp) j -= csp, ++sp, csp = scnt[il + sp * hc];
-            const int u = list[il + sp * hc + 64 * j];
+          unsigned H = 0;
+#pragma unroll
+          for (int s2 = 0; s2 < 8; ++s2)
+            if (s2 < NS) H += (unsigned)scnt[il + s2 * hc];
+          const unsigned q0 = H * (unsigned)sl / (unsigned)NS, q1 = H * (unsigned)(sl + 1) / (unsigned)NS;
+          // locate hit q0 (list sp, entry j); each iteration loads the next entry ahead
+          unsigned j = q0, csp = (unsigned)scnt[il];
+          int sp = 0;
+          if (q0 < q1)
+            while (j >= csp) j -= csp, ++sp, csp = (unsigned)scnt[il + sp * hc];
+          int li = il + sp * hc + 64 * (int)j;
+          int un = q0 < q1 ? list[li] : 0;
+          for (unsigned q = q0; q < q1; ++q) {
+            const int u = un;
+            if (q + 1 < q1) {
+              ++j, li += 64;
+              while (j >= csp) j = 0, ++sp, csp = (unsigned)scnt[il + sp * hc], li = il + sp * hc;
+              un = list[li];
+            }
             const double dx = xi - jp[3 * u], dy = yi - jp[3 * u + 1], dz = zi - jp[3 * u + 2];
             PairAcc<R> acc{{0, 0, 0}, {0, 0, 0}, 0};
             const int cj = MIX ? jc_[u] : 0;
