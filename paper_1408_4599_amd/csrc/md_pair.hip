@@ -435,9 +435,9 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
   write_partial_block<4>(o.partial, acc5, red);
 }
 
-// Staged-partner capacity of the LJ tile: the 48 tile cells at 1.3 x the mean occupancy (+ one
-// wave), rounded to 64; denser neighbourhoods take the chunked fallback.  (Per-lane list entries
-// are 16-bit staged indices, so the cap stays below 65536.)
+// Staged-partner capacity of the LJ tile: the 48 tile cells at 1.12 x the mean occupancy + 32,
+// rounded up to 32, within [256, 4096]; denser tiles take the windowed walk.  (List entries are
+// 16-bit LDS indices of staged entries, 3 per entry, so 3 x 4096 stays below 65536.)
 inline int lj1_tile_cap(int64_t N, int64_t ncell) {
   const double mean = (double)N / (double)ncell;
   int cap = (int)(QCELLS * mean * 1.12) + 32;
