@@ -103,3 +103,46 @@ def test_step_checkpoint_resume_is_bitwise(md):
     for x, y in zip(a[:4], b[:4]):
         np.testing.assert_array_equal(x, y)
     np.testing.assert_array_equal(a[4][20:], b[4])
+
+
+@pytest.mark.parametrize("name", ["c1_ljts_4000", "c4_small"])
+def test_step_nvt_without_energies_row_is_bitwise_the_same(md, name):
+    """md_step with energies = NULL still reduces K(t) for the thermostat: the final state equals
+    the run that also writes the energies row, bit for bit."""
+    cfg = W.make(name)
+    a = _run_gpu(md, cfg, 15, T_target=0.7)
+    m = md.Model(cfg["model"])
+    m.set_thermostat(0.7)
+    cells = md.Cells()
+    pos, vel = dev(cfg["pos"]), dev(cfg["vel"])
+    quat, ang = dev(cfg["quat"]), dev(cfg["angmom"])
+    boxa = np.ascontiguousarray(np.asarray(cfg["box"], dtype=np.float64))
+    md._check(md.lib().md_step(m.handle, cells.handle, md._ptr(pos), md._ptr(vel), md._ptr(quat), md._ptr(ang), None,
+                               pos.shape[0], boxa.ctypes.data_as(md._dp), float(cfg["dt"]), 15, md.PRECISION["fp64"],
+                               None, md._stream()))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(pos.cpu().numpy(), a[0])
+    np.testing.assert_array_equal(vel.cpu().numpy(), a[1])
+    if quat is not None:
+        np.testing.assert_array_equal(quat.cpu().numpy(), a[2])
+        np.testing.assert_array_equal(ang.cpu().numpy(), a[3])
+
+
+def test_step_same_objects_across_sizes(md):
+    """One model and one cells object driven through systems of different N and box (larger,
+    smaller, then the first again): each run equals a run on fresh objects, bit for bit."""
+    base = W.make("c1_ljts_4000")
+    small = W.random_gas(2500, [15.0, 16.0, 17.0], base["model"], seed=21, dmin=0.9)
+    small["vel"] = W.maxwell_velocities(np.random.default_rng(5), np.ones(2500), 1.0)
+    big = W.random_gas(6000, [20.0, 21.0, 22.0], base["model"], seed=22, dmin=0.9)
+    big["vel"] = W.maxwell_velocities(np.random.default_rng(6), np.ones(6000), 1.0)
+    m = md.Model(base["model"])
+    cells = md.Cells()
+    for cfg in (base, big, small, base):
+        pos, vel = dev(cfg["pos"]), dev(cfg["vel"])
+        en = md.step(m, cells, pos, vel, None, None, None, cfg["box"], base["dt"], 5, "fp64")
+        torch.cuda.synchronize()
+        ref = _run_gpu(md, dict(cfg, quat=None, angmom=None, comp=None), 5, dt=base["dt"])
+        np.testing.assert_array_equal(pos.cpu().numpy(), ref[0])
+        np.testing.assert_array_equal(vel.cpu().numpy(), ref[1])
+        np.testing.assert_array_equal(en.cpu().numpy(), ref[4])
