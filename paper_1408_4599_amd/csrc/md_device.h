@@ -69,6 +69,11 @@ template <> __device__ __forceinline__ double rcp_fp64_from<float>(double r2) {
 }
 template <> __device__ __forceinline__ double rcp_fp64_from<double>(double r2) { return rcp_nr<double>(r2); }
 
+// floor(a / b) for 0 <= a < 2^21 and b >= 1 from rb = the FP32 hardware reciprocal of b (1 ulp):
+// (a + 1/2) / b lies at least 1/(2b) from an integer, while the FP32 result is within a relative
+// 2^-22 of it, i.e. within (a + 1/2) 2^-22 / b < 1/(2b).
+__device__ __forceinline__ int div_small(int a, float rb) { return (int)(((float)a + 0.5f) * rb); }
+
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int lane = threadIdx.x & 63;
 #pragma unroll

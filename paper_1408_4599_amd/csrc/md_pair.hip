@@ -275,8 +275,10 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
         __syncthreads();
       }
       LJAcc<R> a;
-      const int NS = hn > 0 ? min(NSMAX, 64 / hn) : 1;
-      const int il = hn > 0 ? lane % hn : 0, sl = hn > 0 ? lane / hn : NS;
+      const float rhn = __builtin_amdgcn_rcpf((float)(hn > 0 ? hn : 1));
+      const int NS = hn > 0 ? min(NSMAX, div_small(64, rhn)) : 1;
+      const int sl = hn > 0 ? div_small(lane, rhn) : NS, il = hn > 0 ? lane - sl * hn : 0;
+      const float rns = __builtin_amdgcn_rcpf((float)NS), r2ns = 0.5f * rns;  // 1/NS, 1/(2 NS)
       const bool act = sl < NS;
       if (hn > 0) {
         const int self = qoff[uh] + il;
@@ -290,7 +292,7 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
         // staged positions: the whole tile (slot = tile index) or this wavefront's window of cq
         // entries, of which the first C are staged at a time
         const int cq = (cap - 16) >> 2;
-        const int C = (cq - 16) / (2 * NS) * (2 * NS);
+        const int C = div_small(cq - 16, r2ns) * (2 * NS);
         const int wb = tiled ? 0 : 3 * wave * cq;  // index into dyn of staged slot 0 (32-bit LDS math)
         // this lane's hit list: entry k at mylist[64 k], holding the LDS index (in doubles) of the
         // staged candidate; lp is the next free entry
@@ -311,7 +313,7 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
 #pragma unroll
             for (int s2 = 0; s2 < NSMAX; ++s2)
               if (s2 < NS) H += (unsigned)scnt[wave][il + s2 * hn];
-            const unsigned q0 = H * (unsigned)sl / (unsigned)NS, q1 = H * (unsigned)(sl + 1) / (unsigned)NS;
+            const unsigned q0 = (unsigned)div_small((int)H * sl, rns), q1 = (unsigned)div_small((int)H * (sl + 1), rns);
             if (q0 < q1) {
               // locate hit q0: list sp, entry j
               unsigned j = q0;
@@ -386,7 +388,7 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
                 if (tail) break;
               }
             };
-            const int cfull = cs + (ce - cs) / (2 * NS) * (2 * NS);
+            const int cfull = cs + div_small(ce - cs, r2ns) * (2 * NS);
             if (d == 1) walk(std::false_type(), std::true_type());
             else walk(std::false_type(), std::false_type());
             if (cfull < ce) {
@@ -673,8 +675,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
       const int rem = min(64 * W, hn - ic), base = rem / W, extra = rem % W;
       const int hc = base + (wave < extra ? 1 : 0);
       const int i0 = ic + wave * base + min(wave, extra);
-      const int NS = hc > 0 ? min(8, 64 / hc) : 1;
-      const int il = hc > 0 ? lane % hc : 0, sl = hc > 0 ? lane / hc : NS;
+      const float rhc = __builtin_amdgcn_rcpf((float)(hc > 0 ? hc : 1));
+      const int NS = hc > 0 ? min(8, div_small(64, rhc)) : 1;
+      const int sl = hc > 0 ? div_small(lane, rhc) : NS, il = hc > 0 ? lane - sl * hc : 0;
+      const float rns = __builtin_amdgcn_rcpf((float)NS);
       const bool act = sl < NS;
       const int sla = act ? sl : 0;
       const int iloc = i0 + il;
@@ -708,7 +712,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
 #pragma unroll
           for (int s2 = 0; s2 < 8; ++s2)
             if (s2 < NS) H += (unsigned)scnt[il + s2 * hc];
-          const unsigned q0 = H * (unsigned)sl / (unsigned)NS, q1 = H * (unsigned)(sl + 1) / (unsigned)NS;
+          const unsigned q0 = (unsigned)div_small((int)H * sl, rns), q1 = (unsigned)div_small((int)H * (sl + 1), rns);
           // locate hit q0 (list sp, entry j); each iteration loads the next entry ahead
           unsigned j = q0, csp = (unsigned)scnt[il];
           int sp = 0;
