@@ -59,8 +59,9 @@ enum {
 
 /* precision argument */
 #define MD_FP64 0 /* all pair arithmetic and accumulation in FP64 */
-#define MD_FP32 1 /* reciprocals, LJ force scalars and multipole terms in FP32; COM test, LJ site
-                     separations, pair energies, accumulation and reductions in FP64 */
+#define MD_FP32 1 /* reciprocals seeded in FP32, single-site LJ force scalars and multipole terms
+                     in FP32; COM test, LJ site separations, multi-site LJ terms, pair energies,
+                     accumulation and reductions in FP64 */
 
 /* device status word bits (md_status) */
 #define MD_DEV_NONFINITE 0x1 /* a position was NaN/Inf */

@@ -12,8 +12,9 @@
 //     fma(dz, dz, fma(dy, dy, dx * dx)) < r_c^2 on d = r_i - (r_j + shift), so the set of
 //     interacting pairs is the brute-force set bit for bit, and lists the hits; pass 2 evaluates
 //     the listed pairs only;
-//   * the FP32 path (R = float) evaluates reciprocals, the LJ force scalar and the multipole
-//     terms in FP32; separations of LJ sites, pair energies and all per-molecule sums are FP64;
+//   * the FP32 path (R = float) seeds reciprocals in FP32 and evaluates the single-site LJ force
+//     scalar and the multipole terms in FP32; separations of LJ sites, the multi-site LJ terms
+//     (which share the energy's FP64 powers), pair energies and all sums are FP64;
 //   * slices are combined in a fixed order; every block writes one row of partials (energy,
 //     virial diagonal, pair count) which a deterministic two-stage reduction sums in order.
 // Every pair is evaluated from both ends (full shell), so no atomics are needed and results are
@@ -564,11 +565,11 @@ __device__ __forceinline__ void elec_group(const CompDev &A, const CompDev &B, c
   }
 }
 
-// One molecule pair seen from i: d = r_i - r_j (FP64, image shift applied).  LJ site separations
-// and energies are formed in FP64 from the FP64 site offsets (vil, vjl); the LJ force scalar and
-// all electrostatic terms are evaluated in R from the site vectors vi and vje (electrostatic slots
-// of j).  gfx950 issues FP64 adds and fmas at the FP32 rate, so only the reciprocals and the
-// multipole polynomials gain from R = float.
+// One molecule pair seen from i: d = r_i - r_j (FP64, image shift applied).  LJ site separations,
+// energies and force scalars are formed in FP64 from the FP64 site offsets (vil, vjl), from one
+// 1/r^2 (FP32-seeded for R = float); all electrostatic terms are evaluated in R from the site
+// vectors vi and vje (electrostatic slots of j).  gfx950 issues FP64 adds and fmas at the FP32
+// rate, so only the reciprocals and the multipole polynomials gain from R = float.
 template <int SL, int SC, int SD, int SQ, bool MIX, typename R>
 __device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci, int cj, const double (*vil)[3],
                                          const R (*vi)[3], const double *vjl, const R *vje, double dxd, double dyd,
@@ -581,29 +582,26 @@ __device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci
   for (int a = 0; a < SL; ++a) {
     if (a >= nla) break;
     const double ax = dxd + vil[a][0], ay = dyd + vil[a][1], az = dzd + vil[a][2];
-    R fa[3] = {(R)0, (R)0, (R)0};  // force on site a from all LJ sites of j (one lever-arm product)
+    double fa[3] = {0.0, 0.0, 0.0};  // force on site a from all LJ sites of j (one lever-arm product)
 #pragma unroll
     for (int b = 0; b < SL; ++b) {
       if (b >= nlb) break;
       const LJPair &p = md->lj[ci][cj][a][b];
       const double rx = ax - vjl[3 * b], ry = ay - vjl[3 * b + 1], rz = az - vjl[3 * b + 2];
       const double r2 = fma(rz, rz, fma(ry, ry, rx * rx));
-      // force scalar in R (FP32: one hardware reciprocal, 1 ulp)
-      R ir2;
-      if constexpr (sizeof(R) == 4) ir2 = __builtin_amdgcn_rcpf((float)r2);
-      else ir2 = rcp_nr<double>(r2);
-      const R s2 = (R)p.sig2 * ir2;
-      const R s6 = s2 * s2 * s2;
-      const R fs = ((R)p.eps24 * ir2) * (s6 * fma((R)2, s6, (R)-1));
-      // energy in FP64 (the shift is summed per molecule pair)
+      // 1/r^2 to FP64 accuracy (FP32 path: from the FP32 hardware reciprocal and one FP64 Newton
+      // step), shared by the energy and the force scalar: FP64 arithmetic issues at the FP32 rate,
+      // and one FP64 chain costs fewer instructions than an FP32 force chain plus conversions
       const double ir2d = rcp_fp64_from<R>(r2);
       const double s2d = p.sig2 * ir2d;
       const double s6d = s2d * s2d * s2d;
-      acc.u = fma(p.eps4 * s6d, s6d - 1.0, acc.u);
-      fa[0] += fs * (R)rx, fa[1] += fs * (R)ry, fa[2] += fs * (R)rz;
+      acc.u = fma(p.eps4 * s6d, s6d - 1.0, acc.u);  // the shift is summed per molecule pair
+      const double fs = (p.eps24 * ir2d) * (s6d * fma(2.0, s6d, -1.0));
+      fa[0] = fma(fs, rx, fa[0]), fa[1] = fma(fs, ry, fa[1]), fa[2] = fma(fs, rz, fa[2]);
     }
-    acc.F[0] += fa[0], acc.F[1] += fa[1], acc.F[2] += fa[2];
-    cross_acc(acc.T, vi[a], fa);
+    const R fr[3] = {(R)fa[0], (R)fa[1], (R)fa[2]};
+    acc.F[0] += fr[0], acc.F[1] += fr[1], acc.F[2] += fr[2];
+    cross_acc(acc.T, vi[a], fr);
   }
   const R dx = (R)dxd, dy = (R)dyd, dz = (R)dzd;
   const R *vj = vje;
