@@ -118,6 +118,8 @@ struct md_model {
   double *force = nullptr, *torque = nullptr, *uw = nullptr;
   int64_t cap_step = 0;
   double T_target = 0.0;        // velocity-rescaling thermostat (0: NVE)
+  int lds_limit = 0;            // LDS bytes per block on the model's device (queried at first use)
+  int lj1_static_lds[2] = {-1, -1};  // static LDS of the single-site pair kernel (FP64, FP32)
   // profiling
   bool profiling = false;
   struct Ev {

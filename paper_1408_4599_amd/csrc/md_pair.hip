@@ -919,10 +919,31 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
   const bool f32 = precision == MD_FP32;
   if (m->single_site) {
     const LJPair p = m->host.lj[0][0][0][0];
-    const int cap = std::max(lj1_tile_cap(c->N, c->ncell), 256 * 8 / 3 + 1);
-    const int lcap = lj1_list_cap(c->N, c->box[0] * c->box[1] * c->box[2], m->host.rc, c->ncell);
-    const size_t lds = std::max((size_t)cap * 3 * sizeof(double), (size_t)256 * 8 * sizeof(double)) +
-                       (size_t)lcap * 256 * sizeof(unsigned short);
+    int cap = std::max(lj1_tile_cap(c->N, c->ncell), 256 * 8 / 3 + 1);
+    int lcap = lj1_list_cap(c->N, c->box[0] * c->box[1] * c->box[2], m->host.rc, c->ncell);
+    auto dyn_lds = [](int cp, int lc) {
+      return std::max((size_t)cp * 3 * sizeof(double), (size_t)256 * 8 * sizeof(double)) +
+             (size_t)lc * 256 * sizeof(unsigned short);
+    };
+    // stay within the device's LDS per block: shrink the tile first (tiles beyond it take the
+    // windowed walk), then the hit lists (which flush earlier); results do not depend on either
+    // beyond rounding
+    if (!m->lds_limit) {
+      int dev = 0, v = 0;
+      if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+        m->lds_limit = v;
+      else
+        m->lds_limit = 64 * 1024;
+    }
+    if (m->lj1_static_lds[f32] < 0) {
+      hipFuncAttributes fa{};
+      const void *k = f32 ? (const void *)k_pair_lj1<float> : (const void *)k_pair_lj1<double>;
+      m->lj1_static_lds[f32] = hipFuncGetAttributes(&fa, k) == hipSuccess ? (int)fa.sharedSizeBytes : 4096;
+    }
+    const size_t stat = (size_t)m->lj1_static_lds[f32];
+    while (stat + dyn_lds(cap, lcap) > (size_t)m->lds_limit && cap > 683) cap = std::max(683, cap - 64);
+    while (stat + dyn_lds(cap, lcap) > (size_t)m->lds_limit && lcap > 16) lcap -= 4;
+    const size_t lds = dyn_lds(cap, lcap);
     const int64_t nq = pair_blocks((int64_t)c->nc[0] * ((c->nc[1] + 1) / 2) * ((c->nc[2] + 1) / 2));
     *nblocks = nq;
     if (f32) k_pair_lj1<float><<<(unsigned)nq, 256, lds, s>>>(cd, p, m->host.rc2, o, cap, lcap);

@@ -111,7 +111,7 @@ def test_cells_one_object_across_grids(md, oracle):
 
 
 FORCE_CASES = ["c1_ljts_4000", "c3_small", "c4_small", "c5_small", "mixture_small", "gas_ragged", "one_cell",
-               "c5_dilute", "mixture_dilute", "mixture4_small"]
+               "c5_dilute", "mixture_dilute", "mixture4_small", "dense_lj"]
 
 
 def _ms_cluster(n_cluster, n_background, seed):
@@ -146,6 +146,8 @@ def _force_cfg(name):
         return W.random_gas(400, [14.0, 15.0, 16.5], W.four_site_model(), seed=17, T=1.2, dmin=1.0)
     if name == "mixture_dilute":
         return W.random_gas(400, [13.0, 15.0, 17.0], W.mixture_model(), seed=19, T=1.5, dmin=1.0)
+    if name == "dense_lj":  # ~40 molecules per cell: the largest staged tiles and hit lists
+        return W.random_gas(2600, [12.0, 12.0, 12.0], W.lj_model(2.5), seed=33, dmin=0.7)
     return W.make(name)
 
 
