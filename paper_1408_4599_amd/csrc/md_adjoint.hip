@@ -341,7 +341,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
       const bool lead = lane < hc;
       const CompDev &cd = md->comp[ci];
       double q[4] = {1.0, 0.0, 0.0, 0.0};
-      int orig = 0;
+      int64_t orig = 0;
       if (lead) {
         orig = c.perm[hs + iloc];
         if (quat)

@@ -128,7 +128,7 @@ __device__ void lj1_cell_chunked(const CellsDev &c, const LJPair &p, double rc2,
       }
     }
     if (act && sl == 0) {
-      const int orig = c.perm[hs + iloc];
+      const int64_t orig = c.perm[hs + iloc];  // 64-bit: 3 orig exceeds 2^31 beyond 7e8 molecules
       a.u -= (double)a.n * p.shift;
       o.force[3 * orig] = a.fx, o.force[3 * orig + 1] = a.fy, o.force[3 * orig + 2] = a.fz;
       if (o.torque) o.torque[3 * orig] = 0.0, o.torque[3 * orig + 1] = 0.0, o.torque[3 * orig + 2] = 0.0;
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
       // tile needs that much slack
       const bool tiled = U + 16 <= cap;  // block-uniform
       // the permutation entry of this lane's home molecule, needed only at the end
-      const int orig = lane < hn ? c.perm[hs + lane] : 0;
+      const int orig32 = lane < hn ? c.perm[hs + lane] : 0;
       if (tiled) {
         // stage by x-rows of three cells (contiguous in the sorted arrays unless x wraps): wave w
         // takes rows w, w + 4, w + 8, w + 12, first entries of all four rows loaded together
@@ -419,6 +419,7 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
           for (int q = 0; q < 8; ++q) v[q] += sred[q * 64 + lane + s * hn];
         const double nn = v[7];
         const double u = v[3] - nn * p.shift;
+        const int64_t orig = orig32;  // 64-bit: 3 orig exceeds 2^31 beyond 7e8 molecules
         o.force[3 * orig] = v[0], o.force[3 * orig + 1] = v[1], o.force[3 * orig + 2] = v[2];
         if (o.torque) o.torque[3 * orig] = 0.0, o.torque[3 * orig + 1] = 0.0, o.torque[3 * orig + 2] = 0.0;
         if (o.u_mol) o.u_mol[orig] = 0.5 * u;
@@ -798,7 +799,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
               dn += n0;
       }
       if (lane < hc) {
-        const int orig = c.perm[hs + iloc];
+        const int64_t orig = c.perm[hs + iloc];  // 64-bit: 3 orig exceeds 2^31 beyond 7e8 molecules
         o.force[3 * orig] = fx, o.force[3 * orig + 1] = fy, o.force[3 * orig + 2] = fz;
         if (o.torque) o.torque[3 * orig] = tx, o.torque[3 * orig + 1] = ty, o.torque[3 * orig + 2] = tz;
         if (o.u_mol) o.u_mol[orig] = 0.5 * uu;
