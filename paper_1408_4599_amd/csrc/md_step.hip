@@ -71,23 +71,30 @@ __device__ __forceinline__ void block_partial(const double (&v)[n], double *part
   }
 }
 
-// Translational kick-drift, one thread per Cartesian component (3N threads, coalesced): v += dt F/m,
-// r = wrap(r + dt v); K_trans from the mid-step velocity.
+// Translational kick-drift over the 3N Cartesian components, LF_PER per thread (block b takes
+// components [b 256 LF_PER, (b + 1) 256 LF_PER), thread j components j, j + 256, ...: every
+// access coalesced, LF_PER loads in flight per thread): v += dt F / m, r = wrap(r + dt v); K_trans
+// from the mid-step velocity.
+constexpr int LF_PER = 4;
 __global__ __launch_bounds__(256) void k_leapfrog_trans(LeapArgs a) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * (256 * LF_PER) + threadIdx.x;
   double kt = 0.0;
-  if (t < 3 * a.N) {
-    const int64_t i = t / 3;
-    const int k = (int)(t - 3 * i);
-    int c = a.comp ? a.comp[i] : 0;
-    if (c < 0 || c >= a.md->ncomp) c = 0;
-    const double mass = a.md->comp[c].mass;
-    const double vold = a.vel[t];
-    const double vnew = vold + a.dt * a.force[t] / mass;
-    const double vmid = 0.5 * (vold + vnew);
-    kt = 0.5 * mass * (vmid * vmid);
-    a.vel[t] = vnew;
-    a.pos[t] = wrap1(a.pos[t] + a.dt * vnew, k == 0 ? a.Lx : (k == 1 ? a.Ly : a.Lz));
+#pragma unroll
+  for (int r = 0; r < LF_PER; ++r) {
+    const int64_t t = base + 256 * r;
+    if (t < 3 * a.N) {
+      const int64_t i = t / 3;
+      const int k = (int)(t - 3 * i);
+      int c = a.comp ? a.comp[i] : 0;
+      if (c < 0 || c >= a.md->ncomp) c = 0;
+      const double mass = a.md->comp[c].mass;
+      const double vold = a.vel[t];
+      const double vnew = vold + a.dt * a.force[t] / mass;
+      const double vmid = 0.5 * (vold + vnew);
+      kt += 0.5 * mass * (vmid * vmid);
+      a.vel[t] = vnew;
+      a.pos[t] = wrap1(a.pos[t] + a.dt * vnew, k == 0 ? a.Lx : (k == 1 ? a.Ly : a.Lz));
+    }
   }
   const double kv[1] = {kt};
   block_partial(kv, a.partial, blockIdx.x, 0);
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(256) void k_rescale(double *vel, double *angmom, co
 int launch_leapfrog(md_model *m, double *pos, double *vel, double *quat, double *angmom, const int32_t *comp,
                     int64_t N, const double box[3], double dt, const double *force, const double *torque,
                     double *kin_rows, int64_t *kin_nrows, hipStream_t s) {
-  const int64_t nt = (3 * N + 255) / 256;
+  const int64_t nt = (3 * N + 256 * LF_PER - 1) / (256 * LF_PER);
   const bool rot = !m->single_site && quat && angmom;
   const int64_t nr = rot ? (N + 255) / 256 : 0;
   LeapArgs a{pos, vel, rot ? quat : nullptr, rot ? angmom : nullptr, comp, N, box[0], box[1],
