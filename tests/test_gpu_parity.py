@@ -253,3 +253,13 @@ def test_box_too_small_is_rejected(md):
     with pytest.raises(md.MDError) as e:
         md.build_cells(m, cells, dev(np.zeros((4, 3))), None, None, [7.4, 10.0, 10.0])
     assert e.value.code == md.MD_EBOX
+
+
+def test_thermostat_argument_errors(md):
+    m = md.Model(W.lj_model(2.5))
+    for T, code in ((-1.0, md.MD_EINVAL), (math.nan, md.MD_ENONFINITE), (math.inf, md.MD_ENONFINITE)):
+        with pytest.raises(md.MDError) as e:
+            m.set_thermostat(T)
+        assert e.value.code == code
+    m.set_thermostat(0.0)
+    m.set_thermostat(1.5)

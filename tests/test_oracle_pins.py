@@ -466,17 +466,23 @@ def test_long_range_correction_matches_quadrature(oracle, case):
     assert oracle.long_range_correction(dict(m, lj_shift=True), counts, box) == (0.0, 0.0)
 
 
-@pytest.mark.parametrize("kind", ["ljts", "2cljq"])
+@pytest.mark.parametrize("kind", ["ljts", "2cljq", "mixture4"])
 def test_velocity_rescaling_thermostat(oracle, kind):
     """NVT by velocity rescaling (Sec. 2): one step with the thermostat equals one step without it
     followed by v <- beta v, j <- beta j with beta = sqrt(T_target / T(t)), where the test forms
-    T(t) = 2 K(t) / f itself (k_B = 1; f = 3N + 2 per linear molecule, the 2CLJQ has I_z = 0)."""
+    T(t) = 2 K(t) / f itself (k_B = 1; f = 3N + 2 per linear molecule, the 2CLJQ has I_z = 0;
+    the four-component mixture mixes asymmetric tops, a linear molecule and a non-rotating one)."""
     if kind == "ljts":
         c = W.random_gas(300, [9.0, 9.0, 9.0], W.lj_model(2.5), seed=5, dmin=0.9)
         m, pos, quat, comp, box = c["model"], c["pos"], None, None, c["box"]
         vel = W.maxwell_velocities(np.random.default_rng(3), np.ones(300), 1.3)
         angmom = None
         f = 3 * 300
+    elif kind == "mixture4":
+        c = W.make("mixture4_small")
+        m, pos, quat, comp, box = c["model"], c["pos"], c["quat"], c["comp"], c["box"]
+        vel, angmom = c["vel"], c["angmom"]
+        f = 3 * len(pos) + sum(int(np.sum(np.asarray(m["components"][k]["inertia"]) > 0)) for k in comp)
     else:
         m = W.twoclj_q_model(rc=4.0)
         c = W.random_gas(120, [12.5, 12.5, 12.5], m, seed=6, dmin=1.3)
@@ -495,4 +501,7 @@ def test_velocity_rescaling_thermostat(oracle, kind):
     beta = math.sqrt(T_target / (2.0 * K / f))
     np.testing.assert_allclose(v1, beta * v0, rtol=1e-14, atol=0)
     if angmom is not None:
-        np.testing.assert_allclose(j1, beta * j0, rtol=1e-14, atol=0)
+        rot = np.ones(len(j0), dtype=bool) if comp is None else np.array(
+            [np.any(np.asarray(m["components"][k]["inertia"]) > 0) for k in comp])
+        np.testing.assert_allclose(j1[rot], beta * j0[rot], rtol=1e-14, atol=0)
+        np.testing.assert_array_equal(j1[~rot], j0[~rot])  # molecules without inertia keep j
