@@ -9,6 +9,7 @@
   the Euler identities of the parameter gradients (U_LJ is homogeneous of degree 1 in the site
   epsilons; dipole and quadrupole energies of degree 2 in their moments)."""
 import json
+import math
 import os
 
 import numpy as np
@@ -103,3 +104,55 @@ def test_full_size_adjoint_properties(md, name):
         assert col == par.shape[0]
         print(f"{name} {prec}: Euler identity rel err {abs(acc - U) / abs(U):.2e}", flush=True)
         assert acc == pytest.approx(U, rel=bar)
+
+
+def test_fcc_lattice_beyond_32_bit_component_indices(md):
+    """Maximum size: a perfect FCC LJTS crystal of 4 x 565^3 = 721 448 500 molecules (3 N passes
+    2^31, so per-molecule outputs need 64-bit addressing), generated on the device.  Every
+    molecule must feel zero force, count the 54 lattice neighbours inside r_c and carry the
+    per-molecule energy of the integer lattice-vector sum, in both precisions."""
+    if torch.cuda.get_device_properties(0).total_memory < 150 * 2 ** 30:
+        pytest.skip("needs ~90 GiB of device memory")
+    n, rho, rc = 565, 0.8, 2.5
+    a = (4.0 / rho) ** (1.0 / 3.0)
+    N = 4 * n ** 3
+    assert 3 * N > 2 ** 31
+    # expected: half the LJTS energies over the lattice vectors (a/2)(h, k, l), h + k + l even
+    u_expected, nn = 0.0, 0
+    shift = 4.0 * (rc ** -12 - rc ** -6)
+    for h in range(-4, 5):
+        for k in range(-4, 5):
+            for l in range(-4, 5):
+                if (h + k + l) % 2 or (h, k, l) == (0, 0, 0):
+                    continue
+                r = 0.5 * a * math.sqrt(h * h + k * k + l * l)
+                if r < rc:
+                    u_expected += 0.5 * (4.0 * (r ** -12 - r ** -6) - shift)
+                    nn += 1
+    assert nn == 54
+    pos = torch.empty((N, 3), dtype=torch.float64, device="cuda")
+    cell = torch.arange(n ** 3, dtype=torch.int64, device="cuda")
+    ijk = torch.stack((cell % n, (cell // n) % n, cell // (n * n)), dim=1).to(torch.float64)
+    del cell
+    view = pos.view(n ** 3, 4, 3)
+    for b, off in enumerate(((0.0, 0.0, 0.0), (0.5, 0.5, 0.0), (0.5, 0.0, 0.5), (0.0, 0.5, 0.5))):
+        view[:, b, :] = (ijk + torch.tensor(off, dtype=torch.float64, device="cuda")) * a
+    del ijk, view
+    box = [n * a] * 3
+    m = md.Model(W.lj_model(rc, shift=True))
+    cells = md.Cells()
+    md.build_cells(m, cells, pos, None, None, box)
+    del pos
+    for prec, fbar in (("fp64", 1e-9), ("fp32", 1e-5)):
+        f = md.forces(m, cells, prec, torque=False, per_molecule=True)
+        fmax = float(f["force"].abs().max())
+        umin, umax = float(f["u_mol"].min()), float(f["u_mol"].max())
+        nmin, nmax = int(f["nnb"].min()), int(f["nnb"].max())
+        print(f"{prec}: N={N} |F|max {fmax:.2e} u in [{umin:.15f}, {umax:.15f}] expected {u_expected:.15f} "
+              f"nnb in [{nmin}, {nmax}]", flush=True)
+        assert nmin == nmax == nn
+        assert int(f["npairs"][0]) == N * nn // 2
+        assert fmax < fbar
+        assert abs(umin - u_expected) < 1e-9 * abs(u_expected) and abs(umax - u_expected) < 1e-9 * abs(u_expected)
+        assert float(f["uw"][0]) == pytest.approx(N * u_expected, rel=1e-9)
+        del f
