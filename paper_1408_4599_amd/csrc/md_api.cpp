@@ -254,7 +254,9 @@ int md_model_create(const md_component_desc *comps, int32_t ncomp, const double 
       (rcode = dalloc((void **)&m->status, sizeof(int32_t), "status")) ||
       (rcode = check_hip(hipMemset(m->status, 0, sizeof(int32_t)), "hipMemset(status)")) ||
       (rcode = dalloc((void **)&m->red2, sizeof(double) * 256 * 256, "reduction")) ||
-      (rcode = dalloc((void **)&m->uw, sizeof(double) * 64, "sums"))) {
+      (rcode = dalloc((void **)&m->uw, sizeof(double) * 64, "sums")) ||
+      (!m->single_site && ((rcode = dalloc((void **)&m->bad, sizeof(unsigned long long) * (1 + BAD_CAP), "fix-up list")) ||
+                           (rcode = check_hip(hipMemset(m->bad, 0, sizeof(unsigned long long)), "hipMemset(fix-up list)"))))) {
     md_model_destroy(m);
     return rcode;
   }
@@ -268,6 +270,8 @@ int md_model_destroy(md_model *m) {
   dfree(m->dev);
   dfree(m->status);
   dfree(m->partial);
+  dfree(m->rows);
+  dfree(m->bad);
   dfree(m->red2);
   dfree(m->pgrad);
   dfree(m->force);
@@ -395,7 +399,9 @@ static int forces_impl(md_model *m, const md_cells *c, int precision, double *fo
   if ((rc = grow(m->partial, m->cap_partial,
                  nb * PARTIAL_COLS + KIN_COLS * ((3 * c->N + 255) / 256 + (c->N + 255) / 256), "partial")))
     return rc;
-  PairOut o{force, torque, u_mol, w_mol, nnb_mol, m->partial};
+  const int nq = (u_mol || w_mol || nnb_mol) ? 9 : 6;
+  if (!m->single_site && (rc = grow(m->rows, m->cap_rows, (int64_t)N3_ROWS * c->N * nq, "pair rows"))) return rc;
+  PairOut o{force, torque, u_mol, w_mol, nnb_mol, m->partial, m->rows, c->N, nq, m->status, m->bad};
   int64_t nblocks = 0;
   hipEvent_t ev;
   prof_begin(m, PROF_PAIR, s, &ev);

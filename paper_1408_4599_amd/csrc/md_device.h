@@ -84,6 +84,30 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
   return v;
 }
 
+// ---------------------------------------------------------------- exact order-free sums
+// FP64 values summed in LDS as 64-bit integers, so that the result does not depend on the order in
+// which concurrent lanes add (the j-side sums of the half-shell pair kernel).  x (|x| < 2^50) is
+// split into h = round(x) and the residual x - h (exact, |x - h| <= 1/2), which is scaled by 2^50
+// and rounded: absolute resolution 2^-51.  Adding the constant M = 1.5 2^52 to a value v with
+// |v| < 2^51 leaves M + round(v) in FP64, whose bit pattern is that of M plus round(v): the raw
+// patterns are summed and the count of terms times the pattern of M is subtracted at the end.
+constexpr double FX_MAGIC = 6755399441055744.0;  // 1.5 * 2^52
+
+__device__ __forceinline__ bool fx_add(unsigned long long *hi, unsigned long long *lo, double x) {
+  const double a = x + FX_MAGIC;
+  const double h = a - FX_MAGIC;
+  const double b = fma(x - h, 0x1p50, FX_MAGIC);
+  atomicAdd(hi, (unsigned long long)__double_as_longlong(a));
+  atomicAdd(lo, (unsigned long long)__double_as_longlong(b));
+  return fabs(x) < 0x1p50;  // false also for NaN
+}
+
+// The value of k terms added with fx_add.
+__device__ __forceinline__ double fx_value(unsigned long long hi, unsigned long long lo, unsigned k) {
+  const unsigned long long m = (unsigned long long)__double_as_longlong(FX_MAGIC) * (unsigned long long)k;
+  return (double)(long long)(hi - m) + (double)(long long)(lo - m) * 0x1p-50;
+}
+
 // ---------------------------------------------------------------- neighbour-cell table
 struct NbTable {
   int off[28];   // exclusive prefix of the 27 cell counts (off[27] = total staged)
@@ -94,12 +118,19 @@ struct NbTable {
 // Stencil entry k = 0..26 is (dx, dy, dz) = (k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1); entry 13
 // is the home cell.  A neighbour index that leaves the grid wraps around, and the molecules of
 // the wrapped cell are seen through the image shift -L (from below) or +L (from above).
+// HALF (Newton's third law): only entries 13..26, stored as k = 0..13 -- the home cell first,
+// then the 13 offsets that follow (0, 0, 0) in (dz, dy, dx) order.  Of two cells at opposite
+// offsets exactly one lists the other, so every unordered pair of a cell and a periodic image of
+// a neighbour is visited once; off[14..27] hold the total.
+template <bool HALF = false>
 __device__ __forceinline__ void build_nb(const CellsDev &c, int cell, NbTable &t) {
+  constexpr int NE = HALF ? 14 : 27, E0 = HALF ? 13 : 0;
   const int lane = threadIdx.x;
   int cnt = 0;
-  if (lane < 27) {
+  if (lane < NE) {
+    const int e = lane + E0;
     const int cx = cell % c.nx, cy = (cell / c.nx) % c.ny, cz = cell / (c.nx * c.ny);
-    int x = cx + lane % 3 - 1, y = cy + (lane / 3) % 3 - 1, z = cz + lane / 9 - 1;
+    int x = cx + e % 3 - 1, y = cy + (e / 3) % 3 - 1, z = cz + e / 9 - 1;
     double shx = 0.0, shy = 0.0, shz = 0.0;
     if (x < 0) x += c.nx, shx = -c.Lx;
     else if (x >= c.nx) x -= c.nx, shx = c.Lx;
@@ -116,8 +147,9 @@ __device__ __forceinline__ void build_nb(const CellsDev &c, int cell, NbTable &t
     t.sh[lane][2] = shz;
   }
   const int incl = wave_incl_scan(cnt);
-  if (lane < 27) t.off[lane] = incl - cnt;
-  if (lane == 26) t.off[27] = incl;
+  if (lane < NE) t.off[lane] = incl - cnt;
+  const int tot = __shfl(incl, NE - 1, 64);
+  if (lane >= NE && lane < 28) t.off[lane] = tot;
 }
 
 // Last stencil entry k with off[k] <= g (skips empty cells).

@@ -70,8 +70,20 @@ struct PairOut {
   double *force, *torque, *u_mol, *w_mol;
   int32_t *nnb_mol;
   double *partial;  // [gridDim.x][PARTIAL_COLS]
+  // half-shell multi-site kernel: per-molecule rows [N3_ROWS][N][nq] in sorted order (row 0 the
+  // molecule's own sums, row 1 + k the partner sums from the cell at half-stencil entry -k),
+  // nq = 6 (force, torque) or 9 (also u, w, partner count), summed by the gather
+  double *rows;
+  int64_t n;
+  int nq;
+  int32_t *status;
+  // partner rows whose terms left the range of the exact LDS sums: bad[0] the count, bad[1 + e]
+  // the row entry (row index x n + sorted molecule index), re-evaluated in FP64 by the fix-up
+  unsigned long long *bad;
 };
-constexpr int PARTIAL_COLS = 5;  // u, wxx, wyy, wzz, nnb
+constexpr int BAD_CAP = 65536;
+constexpr int PARTIAL_COLS = 5;  // u, wxx, wyy, wzz, nnb (the sum of nnb_mol: twice the pair count)
+constexpr int N3_ROWS = 15;
 
 struct AdjOut {
   double gU;
@@ -111,6 +123,9 @@ struct md_model {
   int32_t *status = nullptr;    // device status word
   double *partial = nullptr;    // pair-kernel block partials
   int64_t cap_partial = 0;
+  double *rows = nullptr;       // half-shell per-molecule rows (multi-site)
+  int64_t cap_rows = 0;
+  unsigned long long *bad = nullptr;  // [1 + BAD_CAP] rows for the FP64 fix-up (count first)
   double *red2 = nullptr;       // second-stage reduction buffer
   double *pgrad = nullptr;      // adjoint parameter partials
   int64_t cap_pgrad = 0;

@@ -632,15 +632,23 @@ __device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci
   }
 }
 
-// One block of W wavefronts per home cell.  The 27-cell neighbourhood is staged through LDS in
-// windows of CAP molecules shared by the block (COM position in FP64, LJ site offsets in FP64,
-// electrostatic site vectors in R, component id); the home molecules are split evenly over the
+// One block of W wavefronts per home cell, half shell (Newton's third law, Fig. 1): the home cell
+// and the 13 forward neighbours are staged through LDS in windows of CAP molecules shared by the
+// block (COM position in FP64, LJ site offsets in FP64, electrostatic site vectors in R, component
+// id), home cell first; home molecule i pairs with staged molecule g when g > i (every pair of the
+// home cell once, every forward molecule).  The home molecules are split evenly over the
 // wavefronts, and in a wavefront with n of them lanes are n molecules x NS partner slices
 // (NS = min(8, floor(64 / n))).  Pass 1 runs the exact FP64 COM cutoff test and appends hits
 // (window slots, one byte) to per-lane lists; pass 2 evaluates the listed molecule pairs, the hits
 // of each molecule (its NS lanes' lists in slice order) split into NS contiguous equal parts.
-// Slices are combined with cross-lane reads in a fixed order.  A home cell with more than 64 W
-// molecules is taken 64 W at a time.
+// The molecule's own sums stay in registers (FP64, slices combined in a fixed order) and go to row
+// 0.  The partner receives -F and -tau - d x F (the pair energy is invariant under a rigid
+// rotation of both molecules, so the torques about the two centres and d x F sum to zero), plus
+// half of the pair energy and virial when asked for; these go to per-slot LDS sums in exact
+// integer arithmetic (fx_add), which the block writes, once per window, to the partner's row
+// 1 + k (k its half-stencil entry).  Each (row, molecule) is written by exactly one block, also
+// when its home cell is empty.  A home cell with more than 64 W molecules is taken 64 W at a time;
+// later rounds add to the rows of the first.
 template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP, int W>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 : 3))) void k_pair_ms(CellsDev c, const ModelDev *__restrict__ md, double rc2,
                                                     PairOut o) {
@@ -656,19 +664,31 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
   __shared__ int scnts[W][64];
   __shared__ NbTable nb;
   __shared__ double red[W][5];
+  __shared__ unsigned jn[CAP];  // partner terms per slot
+  __shared__ int jbad[CAP];     // a term of the slot was out of the fixed-point range
+  extern __shared__ unsigned long long jacc[];  // [2 nqf][CAP] partner sums (fx_add pairs)
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   unsigned char *list = lists[wave];
   int *scnt = scnts[wave];
   const int cell = xcd_remap(blockIdx.x, gridDim.x);
+  const bool full = o.nq > 6;
+  const int nqf = full ? 8 : 6;
+  const double shift0 = md->shift_sum[0][0];
   double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  const int hs = cell < c.ncell ? c.cell_start[cell] : 0;
-  const int hn = cell < c.ncell ? __builtin_amdgcn_readfirstlane(c.cell_start[cell + 1] - hs) : 0;
-  if (hn > 0) {
-    if (tid < 64) build_nb(c, cell, nb);
+  if (cell < c.ncell) {
+    const int hs = c.cell_start[cell];
+    const int hn = __builtin_amdgcn_readfirstlane(c.cell_start[cell + 1] - hs);
+    if (tid < 64) build_nb<true>(c, cell, nb);
     __syncthreads();
-    const int M = nb.off[27];
-    const int self0 = nb.off[13];
+    const int M = nb.off[14];
+    if (hn == 0) {  // no home molecules: the partner rows of the half neighbourhood are zero
+      for (int g = tid; g < M; g += 64 * W) {
+        const int k = find_nb(nb.off, g);
+        double *row = o.rows + ((int64_t)(1 + k) * o.n + nb.start[k] + (g - nb.off[k])) * o.nq;
+        for (int q = 0; q < o.nq; ++q) row[q] = 0.0;
+      }
+    }
     for (int ic = 0; ic < hn; ic += 64 * W) {
       // this round's molecules, split evenly over the wavefronts (wave-uniform)
       const int rem = min(64 * W, hn - ic), base = rem / W, extra = rem % W;
@@ -733,11 +753,30 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
             addto(fx, acc.F[0]), addto(fy, acc.F[1]), addto(fz, acc.F[2]);
             addto(tx, acc.T[0]), addto(ty, acc.T[1]), addto(tz, acc.T[2]);
             addto(uu, acc.u);
-            wx = fma(dx, (double)acc.F[0], wx);
-            wy = fma(dy, (double)acc.F[1], wy);
-            wz = fma(dz, (double)acc.F[2], wz);
-            if (MIX) ush += md->shift_sum[ci][cj];
+            const double F0 = acc.F[0], F1 = acc.F[1], F2 = acc.F[2];
+            const double dw = fma(dz, F2, fma(dy, F1, dx * F0));
+            wx = fma(dx, F0, wx);
+            wy = fma(dy, F1, wy);
+            wz = fma(dz, F2, wz);
+            const double sh = MIX ? md->shift_sum[ci][cj] : shift0;
+            if (MIX) ush += sh;
             nn += 1;
+            // partner: -F and -tau - d x F
+            const double T0 = -(double)acc.T[0] - fma(dy, F2, -(dz * F1));
+            const double T1 = -(double)acc.T[1] - fma(dz, F0, -(dx * F2));
+            const double T2 = -(double)acc.T[2] - fma(dx, F1, -(dy * F0));
+            bool ok = fx_add(&jacc[0 * CAP + u], &jacc[1 * CAP + u], -F0);
+            ok &= fx_add(&jacc[2 * CAP + u], &jacc[3 * CAP + u], -F1);
+            ok &= fx_add(&jacc[4 * CAP + u], &jacc[5 * CAP + u], -F2);
+            ok &= fx_add(&jacc[6 * CAP + u], &jacc[7 * CAP + u], T0);
+            ok &= fx_add(&jacc[8 * CAP + u], &jacc[9 * CAP + u], T1);
+            ok &= fx_add(&jacc[10 * CAP + u], &jacc[11 * CAP + u], T2);
+            if (full) {
+              ok &= fx_add(&jacc[12 * CAP + u], &jacc[13 * CAP + u], 0.5 * (acc.u - sh));
+              ok &= fx_add(&jacc[14 * CAP + u], &jacc[15 * CAP + u], 0.5 * dw);
+            }
+            if (!ok) jbad[u] = 1;
+            atomicAdd(&jn[u], 1u);
           }
         }
         cnt = 0;
@@ -761,10 +800,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
           for (int q = 0; q < SL * 3; ++q) jl[t][q] = v[q];
 #pragma unroll
           for (int q = SL * 3; q < NV * 3; ++q) jv[t][q - SL * 3] = (R)v[q];
+          for (int q = 0; q < 2 * nqf; ++q) jacc[q * CAP + t] = 0ull;
+          jn[t] = 0u;
+          jbad[t] = 0;
         }
         __syncthreads();
         if (hc > 0) {
-          const int self = self0 + iloc - jc;  // window slot of the molecule itself (may be outside)
+          const int self = iloc - jc;  // window slot of the molecule itself (may be outside)
           int kb = 0;
           while (true) {
             // pass 1: walk until the window ends or a list could overflow; the slot is always
@@ -776,16 +818,37 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
               const double ra = fma(az, az, fma(ay, ay, ax * ax));
               const double rb = fma(bz_, bz_, fma(by_, by_, bx_ * bx_));
               mylist[64 * cnt] = (unsigned char)ta;
-              cnt += (ta < mj && ra < rc2 && ta != self) ? 1 : 0;
+              cnt += (ta < mj && ra < rc2 && ta > self) ? 1 : 0;
               mylist[64 * cnt] = (unsigned char)tb;
-              cnt += (tb < mj && rb < rc2 && tb != self) ? 1 : 0;
+              cnt += (tb < mj && rb < rc2 && tb > self) ? 1 : 0;
             }
             flush();
             if (kb >= mj) break;
           }
         }
+        __syncthreads();
+        // partner sums of this window to the rows (later rounds add to the first round's)
+        for (int t = tid; t < mj; t += 64 * W) {
+          const int g = jc + t;
+          const int k = find_nb(nb.off, g);
+          const int64_t ent = (int64_t)(1 + k) * o.n + nb.start[k] + (g - nb.off[k]);
+          double *row = o.rows + ent * o.nq;
+          const unsigned K = jn[t];
+          const bool bad = jbad[t] != 0;
+          if (bad) {  // NaN here; listed for the FP64 fix-up
+            const unsigned long long e = atomicAdd(o.bad, 1ull);
+            if (e < BAD_CAP) o.bad[1 + e] = (unsigned long long)ent;
+            else atomicOr(o.status, MD_DEV_RANGE);
+          }
+#pragma unroll 1
+          for (int q = 0; q < o.nq; ++q) {
+            const double v = q < nqf ? (bad ? __builtin_nan("") : fx_value(jacc[2 * q * CAP + t], jacc[(2 * q + 1) * CAP + t], K))
+                                     : (double)K;
+            row[q] = ic == 0 ? v : row[q] + v;
+          }
+        }
       }
-      uu -= MIX ? ush : (double)nn * md->shift_sum[0][0];
+      uu -= MIX ? ush : (double)nn * shift0;
       // slices of molecule il sit in lanes il + s hc: add them to lane il in slice order
       double dn = (double)nn;
       for (int s2 = 1; s2 < NS; ++s2) {
@@ -799,17 +862,120 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
               dn += n0;
       }
       if (lane < hc) {
-        const int64_t orig = c.perm[hs + iloc];  // 64-bit: 3 orig exceeds 2^31 beyond 7e8 molecules
-        o.force[3 * orig] = fx, o.force[3 * orig + 1] = fy, o.force[3 * orig + 2] = fz;
-        if (o.torque) o.torque[3 * orig] = tx, o.torque[3 * orig + 1] = ty, o.torque[3 * orig + 2] = tz;
-        if (o.u_mol) o.u_mol[orig] = 0.5 * uu;
-        if (o.w_mol) o.w_mol[orig] = 0.5 * (wx + wy + wz);
-        if (o.nnb_mol) o.nnb_mol[orig] = (int)dn;
-        acc5[0] += 0.5 * uu, acc5[1] += 0.5 * wx, acc5[2] += 0.5 * wy, acc5[3] += 0.5 * wz, acc5[4] += dn;
+        double *row = o.rows + (int64_t)(hs + iloc) * o.nq;  // row 0: the molecule's own sums
+        row[0] = fx, row[1] = fy, row[2] = fz, row[3] = tx, row[4] = ty, row[5] = tz;
+        if (full) row[6] = 0.5 * uu, row[7] = 0.5 * (wx + wy + wz), row[8] = dn;
+        // each pair once: U, W and W_aa in full, the partner count twice (the sum of nnb_mol)
+        acc5[0] += uu, acc5[1] += wx, acc5[2] += wy, acc5[3] += wz, acc5[4] += 2.0 * dn;
       }
     }
   }
   write_partial_block<W>(o.partial, acc5, red);
+}
+
+// Partner rows listed by the pair kernel because a term left the range of the exact LDS sums
+// (overlapping molecules): each such row is formed again from scratch, every term evaluated as
+// pass 2 evaluates it (same cutoff arithmetic, same pair function, partner terms by the same
+// identities) and summed in FP64 in the order of the home cell's molecules.  Thread per row.
+template <typename R, int SL, int SC, int SD, int SQ, bool MIX>
+__global__ __launch_bounds__(64) void k_pair_fixup(CellsDev c, const ModelDev *__restrict__ md, double rc2,
+                                                   PairOut o) {
+  constexpr int NV = Slots<SL, SC, SD, SQ>::nv;
+  constexpr int NE = NV - SL > 0 ? NV - SL : 1;
+  const unsigned long long cnt = min(o.bad[0], (unsigned long long)BAD_CAP);
+  const bool full = o.nq > 6;
+  for (unsigned long long e = (unsigned long long)blockIdx.x * 64 + threadIdx.x; e < cnt;
+       e += (unsigned long long)gridDim.x * 64) {
+    const int64_t ent = (int64_t)o.bad[1 + e];
+    const int k = (int)(ent / o.n) - 1;  // half-stencil entry of the partner's cell
+    const int64_t src = ent - (int64_t)(k + 1) * o.n;
+    // the partner's cell B: cell_start[B] <= src < cell_start[B + 1]
+    int lo = 0, hi = c.ncell;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (c.cell_start[mid] <= src) lo = mid;
+      else hi = mid;
+    }
+    const int B = lo;
+    // home cell A = B - offset (wrapped) and the image shift of B seen from A, as build_nb forms it
+    const int e13 = k + 13, ox = e13 % 3 - 1, oy = (e13 / 3) % 3 - 1, oz = e13 / 9 - 1;
+    int ax = B % c.nx - ox, ay = (B / c.nx) % c.ny - oy, az = B / (c.nx * c.ny) - oz;
+    ax += ax < 0 ? c.nx : (ax >= c.nx ? -c.nx : 0);
+    ay += ay < 0 ? c.ny : (ay >= c.ny ? -c.ny : 0);
+    az += az < 0 ? c.nz : (az >= c.nz ? -c.nz : 0);
+    const double shx = ax + ox < 0 ? -c.Lx : (ax + ox >= c.nx ? c.Lx : 0.0);
+    const double shy = ay + oy < 0 ? -c.Ly : (ay + oy >= c.ny ? c.Ly : 0.0);
+    const double shz = az + oz < 0 ? -c.Lz : (az + oz >= c.nz ? c.Lz : 0.0);
+    const int A = (az * c.ny + ay) * c.nx + ax;
+    const double jx = c.sx[src] + shx, jy = c.sy[src] + shy, jz = c.sz[src] + shz;
+    double jl[SL * 3];
+    R jv[NE * 3];
+    {
+      const double *v = c.svec + src * NV * 3;
+#pragma unroll
+      for (int q = 0; q < SL * 3; ++q) jl[q] = v[q];
+#pragma unroll
+      for (int q = SL * 3; q < NV * 3; ++q) jv[q - SL * 3] = (R)v[q];
+    }
+    const int cj = MIX ? c.scomp[src] : 0;
+    const int as = c.cell_start[A], an = c.cell_start[A + 1] - as;
+    double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int K = 0;
+    for (int i = 0; i < an; ++i) {
+      if (k == 0 && src - as <= i) continue;  // own cell: partners after the molecule only
+      const int sidx = as + i;
+      const double dx = c.sx[sidx] - jx, dy = c.sy[sidx] - jy, dz = c.sz[sidx] - jz;
+      if (!(fma(dz, dz, fma(dy, dy, dx * dx)) < rc2)) continue;
+      R vi[NV][3];
+      double vil[SL][3];
+      const double *w = c.svec + (int64_t)sidx * NV * 3;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) vi[q][0] = (R)w[3 * q], vi[q][1] = (R)w[3 * q + 1], vi[q][2] = (R)w[3 * q + 2];
+#pragma unroll
+      for (int q = 0; q < SL; ++q) vil[q][0] = w[3 * q], vil[q][1] = w[3 * q + 1], vil[q][2] = w[3 * q + 2];
+      const int ci = MIX ? c.scomp[sidx] : 0;
+      PairAcc<R> acc{{0, 0, 0}, {0, 0, 0}, 0};
+      mol_pair<SL, SC, SD, SQ, MIX, R>(md, ci, cj, vil, vi, jl, jv, dx, dy, dz, acc);
+      const double F0 = acc.F[0], F1 = acc.F[1], F2 = acc.F[2];
+      v[0] -= F0, v[1] -= F1, v[2] -= F2;
+      v[3] += -(double)acc.T[0] - fma(dy, F2, -(dz * F1));
+      v[4] += -(double)acc.T[1] - fma(dz, F0, -(dx * F2));
+      v[5] += -(double)acc.T[2] - fma(dx, F1, -(dy * F0));
+      v[6] += 0.5 * (acc.u - md->shift_sum[ci][cj]);
+      v[7] += 0.5 * fma(dz, F2, fma(dy, F1, dx * F0));
+      ++K;
+    }
+    double *row = o.rows + ent * o.nq;
+    for (int q = 0; q < 6; ++q) row[q] = v[q];
+    if (full) row[6] = v[6], row[7] = v[7], row[8] = (double)K;
+  }
+}
+
+// Sum of the N3_ROWS rows of every molecule and quantity in row order, written in the caller's
+// molecule order (thread per molecule and quantity; row reads coalesced).
+template <int NQ>
+__global__ __launch_bounds__(256) void k_pair_gather(const double *__restrict__ rows, const int32_t *__restrict__ perm,
+                                                    PairOut o) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = o.n * NQ;
+  if (t == 0) o.bad[0] = 0ull;  // the fix-up has run
+  if (t >= tot) return;
+  double v = rows[t];
+#pragma unroll
+  for (int r = 1; r < N3_ROWS; ++r) v += rows[r * tot + t];
+  const int64_t s = t / NQ;
+  const int q = (int)(t - s * NQ);
+  const int64_t orig = perm[s];
+  if (q < 3) o.force[3 * orig + q] = v;
+  else if (q < 6) {
+    if (o.torque) o.torque[3 * orig + q - 3] = v;
+  } else if (q == 6) {
+    if (o.u_mol) o.u_mol[orig] = v;
+  } else if (q == 7) {
+    if (o.w_mol) o.w_mol[orig] = v;
+  } else if (o.nnb_mol) {
+    o.nnb_mol[orig] = (int32_t)v;
+  }
 }
 
 // ---------------------------------------------------------------- deterministic reductions
@@ -886,14 +1052,23 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double *red2
 }
 
 // Dense cells (mean occupancy >= 16) are shared by four wavefronts and staged in larger windows;
-// sparser ones take one wavefront each.
+// sparser ones take one wavefront each.  The partner sums take 2 x 8 bytes per quantity and slot
+// of dynamic LDS.  The gather then forms every molecule's results from its rows.
 template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP1, int CAP4>
 int launch_ms(const CellsDev &cd, const md_model *m, const PairOut &o, int64_t nb, double mean, hipStream_t s) {
+  const size_t per_slot = (size_t)2 * (o.nq > 6 ? 8 : 6) * sizeof(unsigned long long);
   if (mean >= 16.0)
-    k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP4, 4><<<(unsigned)nb, 256, 0, s>>>(cd, m->dev, m->host.rc2, o);
+    k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP4, 4><<<(unsigned)nb, 256, per_slot * CAP4, s>>>(cd, m->dev, m->host.rc2, o);
   else
-    k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP1, 1><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, m->host.rc2, o);
-  return check_hip(hipGetLastError(), "k_pair_ms");
+    k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP1, 1><<<(unsigned)nb, 64, per_slot * CAP1, s>>>(cd, m->dev, m->host.rc2, o);
+  int rc = check_hip(hipGetLastError(), "k_pair_ms");
+  if (rc || o.n == 0) return rc;
+  k_pair_fixup<R, SL, SC, SD, SQ, MIX><<<64, 64, 0, s>>>(cd, m->dev, m->host.rc2, o);
+  if ((rc = check_hip(hipGetLastError(), "k_pair_fixup"))) return rc;
+  const unsigned gb = (unsigned)((o.n * o.nq + 255) / 256);
+  if (o.nq > 6) k_pair_gather<9><<<gb, 256, 0, s>>>(o.rows, cd.perm, o);
+  else k_pair_gather<6><<<gb, 256, 0, s>>>(o.rows, cd.perm, o);
+  return check_hip(hipGetLastError(), "k_pair_gather");
 }
 
 }  // namespace
@@ -954,13 +1129,13 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
   const Shape &S = m->shape;
   const double mean = (double)c->N / (double)c->ncell;
   if (m->fixed_shape && S.lj == 2 && S.chg == 0 && S.dip == 0 && S.quad == 1)
-    return f32 ? launch_ms<float, 2, 0, 0, 1, false, 128, 256>(cd, m, o, nb, mean, s)
-               : launch_ms<double, 2, 0, 0, 1, false, 128, 256>(cd, m, o, nb, mean, s);
+    return f32 ? launch_ms<float, 2, 0, 0, 1, false, 64, 192>(cd, m, o, nb, mean, s)
+               : launch_ms<double, 2, 0, 0, 1, false, 64, 192>(cd, m, o, nb, mean, s);
   if (m->fixed_shape && S.lj == 3 && S.chg == 0 && S.dip == 1 && S.quad == 0)
-    return f32 ? launch_ms<float, 3, 0, 1, 0, false, 128, 256>(cd, m, o, nb, mean, s)
-               : launch_ms<double, 3, 0, 1, 0, false, 128, 256>(cd, m, o, nb, mean, s);
+    return f32 ? launch_ms<float, 3, 0, 1, 0, false, 64, 192>(cd, m, o, nb, mean, s)
+               : launch_ms<double, 3, 0, 1, 0, false, 64, 192>(cd, m, o, nb, mean, s);
   return f32 ? launch_ms<float, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64, 128>(cd, m, o, nb, mean, s)
-             : launch_ms<double, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64, 128>(cd, m, o, nb, mean, s);
+             : launch_ms<double, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64, 96>(cd, m, o, nb, mean, s);
 }
 
 int launch_reduce(md_model *m, int64_t nrows, int ncols, const double *rows, double *out, hipStream_t s) {
