@@ -400,8 +400,13 @@ static int forces_impl(md_model *m, const md_cells *c, int precision, double *fo
                  nb * PARTIAL_COLS + KIN_COLS * ((3 * c->N + 255) / 256 + (c->N + 255) / 256), "partial")))
     return rc;
   const int nq = (u_mol || w_mol || nnb_mol) ? 9 : 6;
-  if (!m->single_site && (rc = grow(m->rows, m->cap_rows, (int64_t)N3_ROWS * c->N * nq, "pair rows"))) return rc;
-  PairOut o{force, torque, u_mol, w_mol, nnb_mol, m->partial, m->rows, c->N, nq, m->status, m->bad};
+  // force/torque rows in the path's precision, then the FP64 u, w, count rows (nq = 9)
+  const int64_t ft_doubles = (int64_t)N3_ROWS * c->N * 6 * (precision == MD_FP32 ? 4 : 8) / 8;
+  if (!m->single_site &&
+      (rc = grow(m->rows, m->cap_rows, ft_doubles + (nq > 6 ? (int64_t)N3_ROWS * c->N * 3 : 0), "pair rows")))
+    return rc;
+  PairOut o{force, torque, u_mol, w_mol, nnb_mol, m->partial, m->rows, m->rows + ft_doubles, c->N, nq, m->status,
+            m->bad};
   int64_t nblocks = 0;
   hipEvent_t ev;
   prof_begin(m, PROF_PAIR, s, &ev);

@@ -70,10 +70,12 @@ struct PairOut {
   double *force, *torque, *u_mol, *w_mol;
   int32_t *nnb_mol;
   double *partial;  // [gridDim.x][PARTIAL_COLS]
-  // half-shell multi-site kernel: per-molecule rows [N3_ROWS][N][nq] in sorted order (row 0 the
-  // molecule's own sums, row 1 + k the partner sums from the cell at half-stencil entry -k),
-  // nq = 6 (force, torque) or 9 (also u, w, partner count), summed by the gather
-  double *rows;
+  // half-shell multi-site kernel: per-molecule rows in sorted order, row 0 the molecule's own
+  // sums, row 1 + k the partner sums from the cell at half-stencil entry -k, summed by the
+  // gather: rows [N3_ROWS][N][6] force and torque in the precision of the path (float or double),
+  // rows_uw [N3_ROWS][N][3] u, w and the partner count in FP64 when nq = 9 (else nq = 6)
+  void *rows;
+  double *rows_uw;
   int64_t n;
   int nq;
   int32_t *status;

@@ -600,9 +600,11 @@ __device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci
       const double fs = (p.eps24 * ir2d) * (s6d * fma(2.0, s6d, -1.0));
       fa[0] = fma(fs, rx, fa[0]), fa[1] = fma(fs, ry, fa[1]), fa[2] = fma(fs, rz, fa[2]);
     }
-    const R fr[3] = {(R)fa[0], (R)fa[1], (R)fa[2]};
-    acc.F[0] += fr[0], acc.F[1] += fr[1], acc.F[2] += fr[2];
-    cross_acc(acc.T, vi[a], fr);
+    acc.F[0] += (R)fa[0], acc.F[1] += (R)fa[1], acc.F[2] += (R)fa[2];
+    // its torque about the centre from the FP64 offset
+    acc.T[0] += (R)(vil[a][1] * fa[2] - vil[a][2] * fa[1]);
+    acc.T[1] += (R)(vil[a][2] * fa[0] - vil[a][0] * fa[2]);
+    acc.T[2] += (R)(vil[a][0] * fa[1] - vil[a][1] * fa[0]);
   }
   const R dx = (R)dxd, dy = (R)dyd, dz = (R)dzd;
   const R *vj = vje;
@@ -645,13 +647,14 @@ __device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci
 // 0.  The partner receives -F and -tau - d x F (the pair energy is invariant under a rigid
 // rotation of both molecules, so the torques about the two centres and d x F sum to zero), plus
 // half of the pair energy and virial when asked for; these go to per-slot LDS sums in exact
-// integer arithmetic (fx_add), which the block writes, once per window, to the partner's row
+// integer arithmetic (fx_add; force and torque terms of the FP32 path one word, fx1_add), which
+// the block writes, once per window, to the partner's row
 // 1 + k (k its half-stencil entry).  Each (row, molecule) is written by exactly one block, also
 // when its home cell is empty.  A home cell with more than 64 W molecules is taken 64 W at a time;
 // later rounds add to the rows of the first.
-template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP, int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 : 3))) void k_pair_ms(CellsDev c, const ModelDev *__restrict__ md, double rc2,
-                                                    PairOut o) {
+template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP, int W, int WPE>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) void k_pair_ms(CellsDev c, const ModelDev *__restrict__ md,
+                                                                                     double rc2, PairOut o) {
   constexpr int NV = Slots<SL, SC, SD, SQ>::nv;
   constexpr int NE = NV - SL > 0 ? NV - SL : 1;  // electrostatic slots
   constexpr int LCAP = 32;
@@ -666,14 +669,18 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
   __shared__ double red[W][5];
   __shared__ unsigned jn[CAP];  // partner terms per slot
   __shared__ int jbad[CAP];     // a term of the slot was out of the fixed-point range
-  extern __shared__ unsigned long long jacc[];  // [2 nqf][CAP] partner sums (fx_add pairs)
+  // partner sums [words][CAP]: force and torque components one word each for R = float (fx1_add),
+  // two for R = double (fx_add), then u and w two words each when asked for
+  extern __shared__ unsigned long long jacc[];
+  constexpr int FW = sizeof(R) == 4 ? 1 : 2;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   unsigned char *list = lists[wave];
   int *scnt = scnts[wave];
   const int cell = xcd_remap(blockIdx.x, gridDim.x);
   const bool full = o.nq > 6;
-  const int nqf = full ? 8 : 6;
+  const int nwords = 6 * FW + (full ? 4 : 0);
+  R *const rft = (R *)o.rows;
   const double shift0 = md->shift_sum[0][0];
   double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (cell < c.ncell) {
@@ -685,8 +692,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
     if (hn == 0) {  // no home molecules: the partner rows of the half neighbourhood are zero
       for (int g = tid; g < M; g += 64 * W) {
         const int k = find_nb(nb.off, g);
-        double *row = o.rows + ((int64_t)(1 + k) * o.n + nb.start[k] + (g - nb.off[k])) * o.nq;
-        for (int q = 0; q < o.nq; ++q) row[q] = 0.0;
+        const int64_t ent = (int64_t)(1 + k) * o.n + nb.start[k] + (g - nb.off[k]);
+        for (int q = 0; q < 6; ++q) rft[6 * ent + q] = (R)0;
+        if (full)
+          for (int q = 0; q < 3; ++q) o.rows_uw[3 * ent + q] = 0.0;
       }
     }
     for (int ic = 0; ic < hn; ic += 64 * W) {
@@ -765,15 +774,16 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
             const double T0 = -(double)acc.T[0] - fma(dy, F2, -(dz * F1));
             const double T1 = -(double)acc.T[1] - fma(dz, F0, -(dx * F2));
             const double T2 = -(double)acc.T[2] - fma(dx, F1, -(dy * F0));
-            bool ok = fx_add(&jacc[0 * CAP + u], &jacc[1 * CAP + u], -F0);
-            ok &= fx_add(&jacc[2 * CAP + u], &jacc[3 * CAP + u], -F1);
-            ok &= fx_add(&jacc[4 * CAP + u], &jacc[5 * CAP + u], -F2);
-            ok &= fx_add(&jacc[6 * CAP + u], &jacc[7 * CAP + u], T0);
-            ok &= fx_add(&jacc[8 * CAP + u], &jacc[9 * CAP + u], T1);
-            ok &= fx_add(&jacc[10 * CAP + u], &jacc[11 * CAP + u], T2);
+            const double pv[6] = {-F0, -F1, -F2, T0, T1, T2};
+            bool ok = true;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+              if constexpr (FW == 1) ok &= fx1_add(&jacc[q * CAP + u], pv[q]);
+              else ok &= fx_add(&jacc[2 * q * CAP + u], &jacc[(2 * q + 1) * CAP + u], pv[q]);
+            }
             if (full) {
-              ok &= fx_add(&jacc[12 * CAP + u], &jacc[13 * CAP + u], 0.5 * (acc.u - sh));
-              ok &= fx_add(&jacc[14 * CAP + u], &jacc[15 * CAP + u], 0.5 * dw);
+              ok &= fx_add(&jacc[6 * FW * CAP + u], &jacc[(6 * FW + 1) * CAP + u], 0.5 * (acc.u - sh));
+              ok &= fx_add(&jacc[(6 * FW + 2) * CAP + u], &jacc[(6 * FW + 3) * CAP + u], 0.5 * dw);
             }
             if (!ok) jbad[u] = 1;
             atomicAdd(&jn[u], 1u);
@@ -800,7 +810,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
           for (int q = 0; q < SL * 3; ++q) jl[t][q] = v[q];
 #pragma unroll
           for (int q = SL * 3; q < NV * 3; ++q) jv[t][q - SL * 3] = (R)v[q];
-          for (int q = 0; q < 2 * nqf; ++q) jacc[q * CAP + t] = 0ull;
+          for (int q = 0; q < nwords; ++q) jacc[q * CAP + t] = 0ull;
           jn[t] = 0u;
           jbad[t] = 0;
         }
@@ -832,7 +842,6 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
           const int g = jc + t;
           const int k = find_nb(nb.off, g);
           const int64_t ent = (int64_t)(1 + k) * o.n + nb.start[k] + (g - nb.off[k]);
-          double *row = o.rows + ent * o.nq;
           const unsigned K = jn[t];
           const bool bad = jbad[t] != 0;
           if (bad) {  // NaN here; listed for the FP64 fix-up
@@ -842,9 +851,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
           }
 #pragma unroll 1
           for (int q = 0; q < o.nq; ++q) {
-            const double v = q < nqf ? (bad ? __builtin_nan("") : fx_value(jacc[2 * q * CAP + t], jacc[(2 * q + 1) * CAP + t], K))
-                                     : (double)K;
-            row[q] = ic == 0 ? v : row[q] + v;
+            const int w = q < 6 ? FW * q : 6 * FW + 2 * (q - 6);  // first word of quantity q
+            const double v = q == 8 ? (double)K
+                             : bad ? __builtin_nan("")
+                             : (q < 6 && FW == 1) ? fx1_value(jacc[w * CAP + t], K)
+                                                  : fx_value(jacc[w * CAP + t], jacc[(w + 1) * CAP + t], K);
+            if (q < 6) rft[6 * ent + q] = ic == 0 ? (R)v : (R)((double)rft[6 * ent + q] + v);
+            else o.rows_uw[3 * ent + q - 6] = ic == 0 ? v : o.rows_uw[3 * ent + q - 6] + v;
           }
         }
       }
@@ -862,9 +875,12 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
               dn += n0;
       }
       if (lane < hc) {
-        double *row = o.rows + (int64_t)(hs + iloc) * o.nq;  // row 0: the molecule's own sums
-        row[0] = fx, row[1] = fy, row[2] = fz, row[3] = tx, row[4] = ty, row[5] = tz;
-        if (full) row[6] = 0.5 * uu, row[7] = 0.5 * (wx + wy + wz), row[8] = dn;
+        R *row = rft + 6 * (int64_t)(hs + iloc);  // row 0: the molecule's own sums
+        row[0] = (R)fx, row[1] = (R)fy, row[2] = (R)fz, row[3] = (R)tx, row[4] = (R)ty, row[5] = (R)tz;
+        if (full) {
+          double *ru = o.rows_uw + 3 * (int64_t)(hs + iloc);
+          ru[0] = 0.5 * uu, ru[1] = 0.5 * (wx + wy + wz), ru[2] = dn;
+        }
         // each pair once: U, W and W_aa in full, the partner count twice (the sum of nnb_mol)
         acc5[0] += uu, acc5[1] += wx, acc5[2] += wy, acc5[3] += wz, acc5[4] += 2.0 * dn;
       }
@@ -945,26 +961,33 @@ __global__ __launch_bounds__(64) void k_pair_fixup(CellsDev c, const ModelDev *_
       v[7] += 0.5 * fma(dz, F2, fma(dy, F1, dx * F0));
       ++K;
     }
-    double *row = o.rows + ent * o.nq;
-    for (int q = 0; q < 6; ++q) row[q] = v[q];
-    if (full) row[6] = v[6], row[7] = v[7], row[8] = (double)K;
+    R *row = (R *)o.rows + 6 * ent;
+    for (int q = 0; q < 6; ++q) row[q] = (R)v[q];
+    if (full) o.rows_uw[3 * ent] = v[6], o.rows_uw[3 * ent + 1] = v[7], o.rows_uw[3 * ent + 2] = (double)K;
   }
 }
 
-// Sum of the N3_ROWS rows of every molecule and quantity in row order, written in the caller's
-// molecule order (thread per molecule and quantity; row reads coalesced).
-template <int NQ>
-__global__ __launch_bounds__(256) void k_pair_gather(const double *__restrict__ rows, const int32_t *__restrict__ perm,
-                                                    PairOut o) {
+// Sum of the N3_ROWS rows of every molecule and quantity in row order (in FP64), written in the
+// caller's molecule order (thread per molecule and quantity; row reads coalesced).
+template <typename R, int NQ>
+__global__ __launch_bounds__(256) void k_pair_gather(const int32_t *__restrict__ perm, PairOut o) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t tot = o.n * NQ;
   if (t == 0) o.bad[0] = 0ull;  // the fix-up has run
-  if (t >= tot) return;
-  double v = rows[t];
-#pragma unroll
-  for (int r = 1; r < N3_ROWS; ++r) v += rows[r * tot + t];
+  if (t >= o.n * NQ) return;
   const int64_t s = t / NQ;
   const int q = (int)(t - s * NQ);
+  double v;
+  if (q < 6) {
+    const R *rows = (const R *)o.rows + 6 * s + q;
+    v = (double)rows[0];
+#pragma unroll
+    for (int r = 1; r < N3_ROWS; ++r) v += (double)rows[r * 6 * o.n];
+  } else {
+    const double *rows = o.rows_uw + 3 * s + q - 6;
+    v = rows[0];
+#pragma unroll
+    for (int r = 1; r < N3_ROWS; ++r) v += rows[r * 3 * o.n];
+  }
   const int64_t orig = perm[s];
   if (q < 3) o.force[3 * orig + q] = v;
   else if (q < 6) {
@@ -1052,22 +1075,26 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double *red2
 }
 
 // Dense cells (mean occupancy >= 16) are shared by four wavefronts and staged in larger windows;
-// sparser ones take one wavefront each.  The partner sums take 2 x 8 bytes per quantity and slot
-// of dynamic LDS.  The gather then forms every molecule's results from its rows.
-template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP1, int CAP4>
+// sparser ones take one wavefront each.  The partner sums take 8 bytes per word and slot of
+// dynamic LDS.  Window sizes and waves per SIMD are chosen per shape and precision so that the
+// LDS of three blocks (or of two where the registers allow only two waves) fits a CU.  The
+// gather then forms every molecule's results from its rows.
+template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP1, int CAP4, int WPE>
 int launch_ms(const CellsDev &cd, const md_model *m, const PairOut &o, int64_t nb, double mean, hipStream_t s) {
-  const size_t per_slot = (size_t)2 * (o.nq > 6 ? 8 : 6) * sizeof(unsigned long long);
+  const size_t per_slot = (size_t)(6 * (sizeof(R) == 4 ? 1 : 2) + (o.nq > 6 ? 4 : 0)) * sizeof(unsigned long long);
   if (mean >= 16.0)
-    k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP4, 4><<<(unsigned)nb, 256, per_slot * CAP4, s>>>(cd, m->dev, m->host.rc2, o);
+    k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP4, 4, WPE>
+        <<<(unsigned)nb, 256, per_slot * CAP4, s>>>(cd, m->dev, m->host.rc2, o);
   else
-    k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP1, 1><<<(unsigned)nb, 64, per_slot * CAP1, s>>>(cd, m->dev, m->host.rc2, o);
+    k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP1, 1, WPE>
+        <<<(unsigned)nb, 64, per_slot * CAP1, s>>>(cd, m->dev, m->host.rc2, o);
   int rc = check_hip(hipGetLastError(), "k_pair_ms");
   if (rc || o.n == 0) return rc;
   k_pair_fixup<R, SL, SC, SD, SQ, MIX><<<64, 64, 0, s>>>(cd, m->dev, m->host.rc2, o);
   if ((rc = check_hip(hipGetLastError(), "k_pair_fixup"))) return rc;
   const unsigned gb = (unsigned)((o.n * o.nq + 255) / 256);
-  if (o.nq > 6) k_pair_gather<9><<<gb, 256, 0, s>>>(o.rows, cd.perm, o);
-  else k_pair_gather<6><<<gb, 256, 0, s>>>(o.rows, cd.perm, o);
+  if (o.nq > 6) k_pair_gather<R, 9><<<gb, 256, 0, s>>>(cd.perm, o);
+  else k_pair_gather<R, 6><<<gb, 256, 0, s>>>(cd.perm, o);
   return check_hip(hipGetLastError(), "k_pair_gather");
 }
 
@@ -1129,13 +1156,13 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
   const Shape &S = m->shape;
   const double mean = (double)c->N / (double)c->ncell;
   if (m->fixed_shape && S.lj == 2 && S.chg == 0 && S.dip == 0 && S.quad == 1)
-    return f32 ? launch_ms<float, 2, 0, 0, 1, false, 64, 192>(cd, m, o, nb, mean, s)
-               : launch_ms<double, 2, 0, 0, 1, false, 64, 192>(cd, m, o, nb, mean, s);
+    return f32 ? launch_ms<float, 2, 0, 0, 1, false, 64, 256, 3>(cd, m, o, nb, mean, s)
+               : launch_ms<double, 2, 0, 0, 1, false, 64, 192, 3>(cd, m, o, nb, mean, s);
   if (m->fixed_shape && S.lj == 3 && S.chg == 0 && S.dip == 1 && S.quad == 0)
-    return f32 ? launch_ms<float, 3, 0, 1, 0, false, 64, 192>(cd, m, o, nb, mean, s)
-               : launch_ms<double, 3, 0, 1, 0, false, 64, 192>(cd, m, o, nb, mean, s);
-  return f32 ? launch_ms<float, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64, 128>(cd, m, o, nb, mean, s)
-             : launch_ms<double, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64, 96>(cd, m, o, nb, mean, s);
+    return f32 ? launch_ms<float, 3, 0, 1, 0, false, 64, 224, 3>(cd, m, o, nb, mean, s)
+               : launch_ms<double, 3, 0, 1, 0, false, 64, 192, 2>(cd, m, o, nb, mean, s);
+  return f32 ? launch_ms<float, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64, 128, 1>(cd, m, o, nb, mean, s)
+             : launch_ms<double, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64, 96, 1>(cd, m, o, nb, mean, s);
 }
 
 int launch_reduce(md_model *m, int64_t nrows, int ncols, const double *rows, double *out, hipStream_t s) {
