@@ -102,16 +102,16 @@ __device__ __forceinline__ bool fx_add(unsigned long long *hi, unsigned long lon
   return fabs(x) < 0x1p50;  // false also for NaN
 }
 
-// Single-word variant for FP32-accurate terms: x scaled by 2^28 and rounded (absolute resolution
-// 2^-29, |x| < 2^22).
+// Single-word variant for FP32-accurate terms: x scaled by 2^26 and rounded (absolute resolution
+// 2^-27, |x| < 2^24).
 __device__ __forceinline__ bool fx1_add(unsigned long long *w, double x) {
-  atomicAdd(w, (unsigned long long)__double_as_longlong(fma(x, 0x1p28, FX_MAGIC)));
-  return fabs(x) < 0x1p22;  // false also for NaN
+  atomicAdd(w, (unsigned long long)__double_as_longlong(fma(x, 0x1p26, FX_MAGIC)));
+  return fabs(x) < 0x1p24;  // false also for NaN
 }
 
 __device__ __forceinline__ double fx1_value(unsigned long long w, unsigned k) {
   const unsigned long long m = (unsigned long long)__double_as_longlong(FX_MAGIC) * (unsigned long long)k;
-  return (double)(long long)(w - m) * 0x1p-28;
+  return (double)(long long)(w - m) * 0x1p-26;
 }
 
 // The value of k terms added with fx_add.

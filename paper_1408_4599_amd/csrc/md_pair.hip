@@ -892,7 +892,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
 // Partner rows listed by the pair kernel because a term left the range of the exact LDS sums
 // (overlapping molecules): each such row is formed again from scratch, every term evaluated as
 // pass 2 evaluates it (same cutoff arithmetic, same pair function, partner terms by the same
-// identities) and summed in FP64 in the order of the home cell's molecules.  Thread per row.
+// identities) and summed in FP64.  One wavefront per row: lane l takes the home molecules
+// l, l + 64, ... in turn, and each round of 64 terms is added by a fixed butterfly, read from
+// lane 0, so the sum is the same on every run.
 template <typename R, int SL, int SC, int SD, int SQ, bool MIX>
 __global__ __launch_bounds__(64) void k_pair_fixup(CellsDev c, const ModelDev *__restrict__ md, double rc2,
                                                    PairOut o) {
@@ -900,8 +902,8 @@ __global__ __launch_bounds__(64) void k_pair_fixup(CellsDev c, const ModelDev *_
   constexpr int NE = NV - SL > 0 ? NV - SL : 1;
   const unsigned long long cnt = min(o.bad[0], (unsigned long long)BAD_CAP);
   const bool full = o.nq > 6;
-  for (unsigned long long e = (unsigned long long)blockIdx.x * 64 + threadIdx.x; e < cnt;
-       e += (unsigned long long)gridDim.x * 64) {
+  const int lane = threadIdx.x;
+  for (unsigned long long e = blockIdx.x; e < cnt; e += gridDim.x) {
     const int64_t ent = (int64_t)o.bad[1 + e];
     const int k = (int)(ent / o.n) - 1;  // half-stencil entry of the partner's cell
     const int64_t src = ent - (int64_t)(k + 1) * o.n;
@@ -935,35 +937,47 @@ __global__ __launch_bounds__(64) void k_pair_fixup(CellsDev c, const ModelDev *_
     }
     const int cj = MIX ? c.scomp[src] : 0;
     const int as = c.cell_start[A], an = c.cell_start[A + 1] - as;
-    double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int K = 0;
-    for (int i = 0; i < an; ++i) {
-      if (k == 0 && src - as <= i) continue;  // own cell: partners after the molecule only
-      const int sidx = as + i;
-      const double dx = c.sx[sidx] - jx, dy = c.sy[sidx] - jy, dz = c.sz[sidx] - jz;
-      if (!(fma(dz, dz, fma(dy, dy, dx * dx)) < rc2)) continue;
-      R vi[NV][3];
-      double vil[SL][3];
-      const double *w = c.svec + (int64_t)sidx * NV * 3;
+    double sum[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i0 = 0; i0 < an; i0 += 64) {
+      const int i = i0 + lane;
+      double v[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      // own cell: partners after the molecule only
+      if (i < an && !(k == 0 && src - as <= i)) {
+        const int sidx = as + i;
+        const double dx = c.sx[sidx] - jx, dy = c.sy[sidx] - jy, dz = c.sz[sidx] - jz;
+        if (fma(dz, dz, fma(dy, dy, dx * dx)) < rc2) {
+          R vi[NV][3];
+          double vil[SL][3];
+          const double *w = c.svec + (int64_t)sidx * NV * 3;
 #pragma unroll
-      for (int q = 0; q < NV; ++q) vi[q][0] = (R)w[3 * q], vi[q][1] = (R)w[3 * q + 1], vi[q][2] = (R)w[3 * q + 2];
+          for (int q = 0; q < NV; ++q) vi[q][0] = (R)w[3 * q], vi[q][1] = (R)w[3 * q + 1], vi[q][2] = (R)w[3 * q + 2];
 #pragma unroll
-      for (int q = 0; q < SL; ++q) vil[q][0] = w[3 * q], vil[q][1] = w[3 * q + 1], vil[q][2] = w[3 * q + 2];
-      const int ci = MIX ? c.scomp[sidx] : 0;
-      PairAcc<R> acc{{0, 0, 0}, {0, 0, 0}, 0};
-      mol_pair<SL, SC, SD, SQ, MIX, R>(md, ci, cj, vil, vi, jl, jv, dx, dy, dz, acc);
-      const double F0 = acc.F[0], F1 = acc.F[1], F2 = acc.F[2];
-      v[0] -= F0, v[1] -= F1, v[2] -= F2;
-      v[3] += -(double)acc.T[0] - fma(dy, F2, -(dz * F1));
-      v[4] += -(double)acc.T[1] - fma(dz, F0, -(dx * F2));
-      v[5] += -(double)acc.T[2] - fma(dx, F1, -(dy * F0));
-      v[6] += 0.5 * (acc.u - md->shift_sum[ci][cj]);
-      v[7] += 0.5 * fma(dz, F2, fma(dy, F1, dx * F0));
-      ++K;
+          for (int q = 0; q < SL; ++q) vil[q][0] = w[3 * q], vil[q][1] = w[3 * q + 1], vil[q][2] = w[3 * q + 2];
+          const int ci = MIX ? c.scomp[sidx] : 0;
+          PairAcc<R> acc{{0, 0, 0}, {0, 0, 0}, 0};
+          mol_pair<SL, SC, SD, SQ, MIX, R>(md, ci, cj, vil, vi, jl, jv, dx, dy, dz, acc);
+          const double F0 = acc.F[0], F1 = acc.F[1], F2 = acc.F[2];
+          v[0] = -F0, v[1] = -F1, v[2] = -F2;
+          v[3] = -(double)acc.T[0] - fma(dy, F2, -(dz * F1));
+          v[4] = -(double)acc.T[1] - fma(dz, F0, -(dx * F2));
+          v[5] = -(double)acc.T[2] - fma(dx, F1, -(dy * F0));
+          v[6] = 0.5 * (acc.u - md->shift_sum[ci][cj]);
+          v[7] = 0.5 * fma(dz, F2, fma(dy, F1, dx * F0));
+          v[8] = 1.0;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) v[q] += __shfl_xor(v[q], m);
+        sum[q] += v[q];
+      }
     }
-    R *row = (R *)o.rows + 6 * ent;
-    for (int q = 0; q < 6; ++q) row[q] = (R)v[q];
-    if (full) o.rows_uw[3 * ent] = v[6], o.rows_uw[3 * ent + 1] = v[7], o.rows_uw[3 * ent + 2] = (double)K;
+    if (lane == 0) {
+      R *row = (R *)o.rows + 6 * ent;
+      for (int q = 0; q < 6; ++q) row[q] = (R)sum[q];
+      if (full) o.rows_uw[3 * ent] = sum[6], o.rows_uw[3 * ent + 1] = sum[7], o.rows_uw[3 * ent + 2] = sum[8];
+    }
   }
 }
 
@@ -1090,7 +1104,7 @@ int launch_ms(const CellsDev &cd, const md_model *m, const PairOut &o, int64_t n
         <<<(unsigned)nb, 64, per_slot * CAP1, s>>>(cd, m->dev, m->host.rc2, o);
   int rc = check_hip(hipGetLastError(), "k_pair_ms");
   if (rc || o.n == 0) return rc;
-  k_pair_fixup<R, SL, SC, SD, SQ, MIX><<<64, 64, 0, s>>>(cd, m->dev, m->host.rc2, o);
+  k_pair_fixup<R, SL, SC, SD, SQ, MIX><<<256, 64, 0, s>>>(cd, m->dev, m->host.rc2, o);
   if ((rc = check_hip(hipGetLastError(), "k_pair_fixup"))) return rc;
   const unsigned gb = (unsigned)((o.n * o.nq + 255) / 256);
   if (o.nq > 6) k_pair_gather<R, 9><<<gb, 256, 0, s>>>(cd.perm, o);

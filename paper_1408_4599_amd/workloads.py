@@ -162,16 +162,44 @@ def angular_momenta(rng, quat, inertia, T):
     return rot.apply(jb)
 
 
-def _system(name, model, pos, box, T, rng, dt, nsteps, comp=None, rotate=True, note=""):
+def orientations_without_overlap(rng, pos, box, site_pos, dmin, max_rounds=200):
+    """Random orientations (uniform on SO(3)) such that no two sites of different molecules are
+    closer than dmin (minimum image): in every round, one molecule of each clashing pair, picked
+    at random, draws a new orientation, until no clash is left."""
+    from scipy.spatial import cKDTree
+    N, box = pos.shape[0], np.asarray(box, dtype=np.float64)
+    site_pos = np.asarray(site_pos, dtype=np.float64)
+    mol = np.repeat(np.arange(N), site_pos.shape[0])
+    quat = random_quaternions(rng, N)
+    for _ in range(max_rounds):
+        w, x, y, z = quat.T
+        A = np.stack([np.stack([w * w + x * x - y * y - z * z, 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+                      np.stack([2 * (x * y + w * z), w * w - x * x + y * y - z * z, 2 * (y * z - w * x)], -1),
+                      np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), w * w - x * x - y * y + z * z], -1)], -2)
+        sites = (pos[:, None, :] + np.einsum("nij,sj->nsi", A, site_pos)).reshape(-1, 3) % box
+        sites = np.where(sites >= box, sites - box, sites)
+        pairs = cKDTree(sites, boxsize=box).query_pairs(dmin, output_type="ndarray")
+        mp = mol[pairs]
+        mp = mp[mp[:, 0] != mp[:, 1]]
+        if len(mp) == 0:
+            return quat
+        bad = np.unique(mp[np.arange(len(mp)), rng.integers(0, 2, size=len(mp))])
+        quat[bad] = random_quaternions(rng, len(bad))
+    raise RuntimeError("orientations_without_overlap: no arrangement found")
+
+
+def _system(name, model, pos, box, T, rng, dt, nsteps, comp=None, rotate=True, note="", quat=None):
     N = pos.shape[0]
     comp = np.zeros(N, dtype=np.int32) if comp is None else np.asarray(comp, dtype=np.int32)
     masses = np.asarray([model["components"][c]["mass"] for c in comp], dtype=np.float64)
     vel = maxwell_velocities(rng, masses, T)
     multi = any(len(c["sites"]) > 1 or c["sites"][0]["kind"] != "lj" or any(v != 0 for v in c["sites"][0]["pos"])
                 for c in model["components"])
-    quat = angmom = None
-    if multi and rotate:
-        quat = random_quaternions(rng, N)
+    angmom = None
+    if not (multi and rotate):
+        quat = None
+    else:
+        quat = random_quaternions(rng, N) if quat is None else quat
         angmom = np.zeros((N, 3))
         for c, cm in enumerate(model["components"]):
             sel = comp == c
@@ -291,13 +319,19 @@ def c4_small():
 
 def c5_four_site(N=200_000, rho=0.4, name="c5_4site_200k", seed=5):
     """Four-site stand-in (3 LJ + dipole mu^2 = 3), rho = 0.4, T = 1.2, random orientations,
-    r_c = 4, reaction field eps_RF = infinity: FCC with random vacancies down to N."""
+    r_c = 4, reaction field eps_RF = infinity: FCC with random vacancies down to N.  The
+    elongated molecules on the lattice would put some LJ sites of neighbours almost on top of each
+    other; orientations are drawn until no two sites of different molecules are closer than
+    0.7 sigma, so that the start state can be integrated at dt = 0.002."""
     rng = rng_for(seed)
     L = (N / rho) ** (1.0 / 3.0)
     nf = int(math.ceil((N / 4) ** (1.0 / 3.0)))
     lat = jitter(rng, fcc_lattice(nf, L / nf))
     keep = np.sort(rng.choice(lat.shape[0], size=N, replace=False))
-    return _system(name, four_site_model(), lat[keep], [L, L, L], 1.2, rng, 0.002, 1000)
+    model = four_site_model()
+    lj = [st["pos"] for st in model["components"][0]["sites"] if st["kind"] == "lj"]
+    quat = orientations_without_overlap(rng, lat[keep], [L, L, L], lj, 0.7)
+    return _system(name, model, lat[keep], [L, L, L], 1.2, rng, 0.002, 1000, quat=quat)
 
 
 def c5_small():
