@@ -68,8 +68,10 @@ enum {
 #define MD_DEV_COMP 0x2      /* a component id was outside [0, ncomp) */
 #define MD_DEV_QUAT 0x4      /* | |q|^2 - 1 | > 1e-6 for some molecule */
 #define MD_DEV_CAPACITY 0x8  /* internal capacity exceeded (should not happen) */
-#define MD_DEV_RANGE 0x10    /* multi-site: a pair force or torque component beyond 2^50 in magnitude
-                                (overlapping molecules); the partner's force and torque are NaN */
+#define MD_DEV_RANGE 0x10    /* multi-site: more than 65 536 partner sums had a pair term beyond the
+                                range of the exact LDS sums (2^24 FP32, 2^23 FP64: overlapping
+                                molecules) and needed the FP64 fix-up; the force and torque of
+                                the partners beyond that number are NaN */
 
 /* compiled limits of the component table */
 #define MD_MAX_COMP 4

@@ -647,7 +647,7 @@ __device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci
 // 0.  The partner receives -F and -tau - d x F (the pair energy is invariant under a rigid
 // rotation of both molecules, so the torques about the two centres and d x F sum to zero), plus
 // half of the pair energy and virial when asked for; these go to per-slot LDS sums in exact
-// integer arithmetic (fx_add; force and torque terms of the FP32 path one word, fx1_add), which
+// integer arithmetic (fx1_add on the FP32 path, fx2_add on the FP64 path, fx_add for u, w), which
 // the block writes, once per window, to the partner's row
 // 1 + k (k its half-stencil entry).  Each (row, molecule) is written by exactly one block, also
 // when its home cell is empty.  A home cell with more than 64 W molecules is taken 64 W at a time;
@@ -669,17 +669,19 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
   __shared__ double red[W][5];
   __shared__ unsigned jn[CAP];  // partner terms per slot
   __shared__ int jbad[CAP];     // a term of the slot was out of the fixed-point range
-  // partner sums [words][CAP]: force and torque components one word each for R = float (fx1_add),
-  // two for R = double (fx_add), then u and w two words each when asked for
+  // partner sums [words][CAP]: force and torque components one 64-bit word each (R = float:
+  // fx1_add; R = double: the low words of fx2_add), then u and w two words each (fx_add) when
+  // asked for; for R = double the 32-bit high words of the force and torque follow, [6][CAP]
   extern __shared__ unsigned long long jacc[];
-  constexpr int FW = sizeof(R) == 4 ? 1 : 2;
+  constexpr bool F64 = sizeof(R) == 8;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   unsigned char *list = lists[wave];
   int *scnt = scnts[wave];
   const int cell = xcd_remap(blockIdx.x, gridDim.x);
   const bool full = o.nq > 6;
-  const int nwords = 6 * FW + (full ? 4 : 0);
+  const int nwords = 6 + (full ? 4 : 0);
+  int *const jhi = (int *)(jacc + nwords * CAP);
   R *const rft = (R *)o.rows;
   const double shift0 = md->shift_sum[0][0];
   double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -778,12 +780,12 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
             bool ok = true;
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
-              if constexpr (FW == 1) ok &= fx1_add(&jacc[q * CAP + u], pv[q]);
-              else ok &= fx_add(&jacc[2 * q * CAP + u], &jacc[(2 * q + 1) * CAP + u], pv[q]);
+              if constexpr (F64) ok &= fx2_add(&jacc[q * CAP + u], &jhi[q * CAP + u], pv[q]);
+              else ok &= fx1_add(&jacc[q * CAP + u], pv[q]);
             }
             if (full) {
-              ok &= fx_add(&jacc[6 * FW * CAP + u], &jacc[(6 * FW + 1) * CAP + u], 0.5 * (acc.u - sh));
-              ok &= fx_add(&jacc[(6 * FW + 2) * CAP + u], &jacc[(6 * FW + 3) * CAP + u], 0.5 * dw);
+              ok &= fx_add(&jacc[6 * CAP + u], &jacc[7 * CAP + u], 0.5 * (acc.u - sh));
+              ok &= fx_add(&jacc[8 * CAP + u], &jacc[9 * CAP + u], 0.5 * dw);
             }
             if (!ok) jbad[u] = 1;
             atomicAdd(&jn[u], 1u);
@@ -811,6 +813,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
 #pragma unroll
           for (int q = SL * 3; q < NV * 3; ++q) jv[t][q - SL * 3] = (R)v[q];
           for (int q = 0; q < nwords; ++q) jacc[q * CAP + t] = 0ull;
+          if constexpr (F64)
+            for (int q = 0; q < 6; ++q) jhi[q * CAP + t] = 0;
           jn[t] = 0u;
           jbad[t] = 0;
         }
@@ -851,11 +855,12 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
           }
 #pragma unroll 1
           for (int q = 0; q < o.nq; ++q) {
-            const int w = q < 6 ? FW * q : 6 * FW + 2 * (q - 6);  // first word of quantity q
-            const double v = q == 8 ? (double)K
-                             : bad ? __builtin_nan("")
-                             : (q < 6 && FW == 1) ? fx1_value(jacc[w * CAP + t], K)
-                                                  : fx_value(jacc[w * CAP + t], jacc[(w + 1) * CAP + t], K);
+            const int w = q < 6 ? q : 6 + 2 * (q - 6);  // first word of quantity q
+            const double v = q == 8   ? (double)K
+                             : bad    ? __builtin_nan("")
+                             : q >= 6 ? fx_value(jacc[w * CAP + t], jacc[(w + 1) * CAP + t], K)
+                             : F64    ? fx2_value(jacc[w * CAP + t], jhi[(q < 6 ? q : 0) * CAP + t], K)
+                                      : fx1_value(jacc[w * CAP + t], K);
             if (q < 6) rft[6 * ent + q] = ic == 0 ? (R)v : (R)((double)rft[6 * ent + q] + v);
             else o.rows_uw[3 * ent + q - 6] = ic == 0 ? v : o.rows_uw[3 * ent + q - 6] + v;
           }
@@ -1095,7 +1100,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double *red2
 // gather then forms every molecule's results from its rows.
 template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP1, int CAP4, int WPE>
 int launch_ms(const CellsDev &cd, const md_model *m, const PairOut &o, int64_t nb, double mean, hipStream_t s) {
-  const size_t per_slot = (size_t)(6 * (sizeof(R) == 4 ? 1 : 2) + (o.nq > 6 ? 4 : 0)) * sizeof(unsigned long long);
+  const size_t per_slot = (size_t)(6 + (o.nq > 6 ? 4 : 0)) * sizeof(unsigned long long) + (sizeof(R) == 8 ? 6 * sizeof(int) : 0);
   if (mean >= 16.0)
     k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP4, 4, WPE>
         <<<(unsigned)nb, 256, per_slot * CAP4, s>>>(cd, m->dev, m->host.rc2, o);
@@ -1174,7 +1179,7 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
                : launch_ms<double, 2, 0, 0, 1, false, 64, 192, 3>(cd, m, o, nb, mean, s);
   if (m->fixed_shape && S.lj == 3 && S.chg == 0 && S.dip == 1 && S.quad == 0)
     return f32 ? launch_ms<float, 3, 0, 1, 0, false, 64, 224, 3>(cd, m, o, nb, mean, s)
-               : launch_ms<double, 3, 0, 1, 0, false, 64, 192, 2>(cd, m, o, nb, mean, s);
+               : launch_ms<double, 3, 0, 1, 0, false, 64, 192, 3>(cd, m, o, nb, mean, s);
   return f32 ? launch_ms<float, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64, 128, 1>(cd, m, o, nb, mean, s)
              : launch_ms<double, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64, 96, 1>(cd, m, o, nb, mean, s);
 }
