@@ -3,9 +3,11 @@
 // torques per molecule).
 //
 // Work decomposition (details above each kernel):
-//   * the 27 cells around each home cell (edge >= r_c, so every partner inside the cutoff is
-//     there, Sec. 3) are staged into LDS with their periodic image shift already applied, shared
-//     by the wavefronts of a block (several home cells, or several wavefronts per dense cell);
+//   * the cells around each home cell (edge >= r_c, so every partner inside the cutoff is there,
+//     Sec. 3) are staged into LDS with their periodic image shift already applied, shared by the
+//     wavefronts of a block (several home cells, or several wavefronts per dense cell): all 27
+//     for single-site LJ, the home cell and its 13 forward neighbours (half shell) for
+//     multi-site molecules;
 //   * the lanes of a wavefront are n molecules x NS = min(8, floor(64 / n)) partner slices, and
 //     lane (i, s) scans staged partners s, s + NS, ...;
 //   * pass 1 runs the COM cutoff test in FP64 with the exact expression
@@ -17,8 +19,11 @@
 //     (which share the energy's FP64 powers), pair energies and all sums are FP64;
 //   * slices are combined in a fixed order; every block writes one row of partials (energy,
 //     virial diagonal, pair count) which a deterministic two-stage reduction sums in order.
-// Every pair is evaluated from both ends (full shell), so no atomics are needed and results are
-// bitwise reproducible.  The pair work is VALU-bound (no dense contraction: no MFMA).
+// Single-site LJ pairs are evaluated from both ends (full shell): no partner sums at all.
+// Multi-site pairs are evaluated once (Newton's third law, Fig. 1); the partner's terms are summed
+// as exact integers in LDS, written to per-molecule rows and added in a fixed order by a gather,
+// so results are bitwise reproducible either way.  The pair work is VALU-bound (no dense
+// contraction: no MFMA).
 
 #include <algorithm>
 #include <cmath>
