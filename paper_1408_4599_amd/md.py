@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libmdcell.so")
 MD_OK, MD_EINVAL, MD_EBOX, MD_ECOMP, MD_ENONFINITE, MD_EHIP, MD_ENOMEM, MD_EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 MD_LJ_SHIFT, MD_CHECK = 0x1, 0x2
 MD_FP64, MD_FP32 = 0, 1
+# device status word bits (Model.status)
+MD_DEV_NONFINITE, MD_DEV_COMP, MD_DEV_QUAT, MD_DEV_CAPACITY, MD_DEV_RANGE = 0x1, 0x2, 0x4, 0x8, 0x10
 PRECISION = {"fp64": MD_FP64, "fp32": MD_FP32, MD_FP64: MD_FP64, MD_FP32: MD_FP32}
 MAX_COMP, MAX_LJ, MAX_CHG, MAX_DIP, MAX_QUAD = 4, 4, 4, 2, 2
 

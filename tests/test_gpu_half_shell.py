@@ -103,3 +103,21 @@ def test_isolated_cluster_conserves_momentum_and_angular_momentum(md):
     L = T.sum(0) + np.cross(c["pos"], F).sum(0)
     scale_L = np.abs(T).sum() + np.abs(np.cross(c["pos"], F)).sum()
     assert np.all(np.abs(L) < 1e-13 * scale_L)
+
+
+def test_fixup_list_overflow_sets_status(md):
+    """More partner sums out of the fixed-point range than the fix-up list holds (65 536 rows):
+    32 768 four-site molecules on a 0.3-spaced grid with r_c = 1.5 (about 97 000 such rows).  The
+    call completes, the status word gets MD_DEV_RANGE, the rows beyond the list give NaN and the
+    others stay finite."""
+    n = 32
+    g = np.stack(np.meshgrid(*[np.arange(n)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    pos = 2.0 + 0.3 * g
+    cfg = {"model": W.four_site_model(rc=1.5), "pos": pos, "quat": W.random_quaternions(W.rng_for(61), len(pos)),
+           "comp": np.zeros(len(pos), dtype=np.int32), "box": np.array([30.0, 30.0, 30.0])}
+    got, m, _ = run_forces(md, cfg, "fp32")
+    st = m.status()
+    bad = ~np.isfinite(got["force"]).all(axis=1)
+    print(f"status {st:#x}, molecules with a NaN force {int(bad.sum())} of {len(pos)}", flush=True)
+    assert st & md.MD_DEV_RANGE
+    assert 0 < bad.sum() < len(pos)
