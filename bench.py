@@ -99,12 +99,13 @@ def pair_counters(kernel_sources):
     return (val, flop) if src == h.hexdigest() else (None, None)
 
 
-def measure_extra(md, W, torch, name, evals, steps, adjoint=False):
-    """Forces-only and md_step throughput of one more workload (FP32 and FP64)."""
+def measure_extra(md, W, torch, name, evals, steps, adjoint=False, half_shell=False):
+    """Forces-only and md_step throughput of one more workload (FP32 and FP64); half_shell selects
+    the half-shell pair kernel for a single-site model (MD_HALF_SHELL)."""
     cfg = W.make(name)
     N = cfg["pos"].shape[0]
     dev = lambda a, dt=torch.float64: None if a is None else torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
-    model = md.Model(cfg["model"])
+    model = md.Model(cfg["model"], half_shell=half_shell)
     cells = md.Cells()
     multi = cfg["quat"] is not None
     md.build_cells(model, cells, dev(cfg["pos"]), dev(cfg["quat"]), None, cfg["box"])
@@ -389,10 +390,12 @@ def main():
 
     if not args.no_extra:
         extra = {}
-        for name, ev, st, adj in (("c3_lj_slab_2m", 20, 20, False), ("c4_2cljq_500k", 10, 10, False),
-                                  ("c5_4site_200k", 10, 10, True)):
-            print(f"[bench] extra workload {name}", file=sys.stderr, flush=True)
-            extra[name] = measure_extra(md, W, torch, name, ev, st, adj)
+        for key, name, ev, st, adj, hs in (("c3_lj_slab_2m", "c3_lj_slab_2m", 20, 20, False, False),
+                                           ("c3_lj_slab_2m_half_shell", "c3_lj_slab_2m", 20, 20, False, True),
+                                           ("c4_2cljq_500k", "c4_2cljq_500k", 10, 10, False, False),
+                                           ("c5_4site_200k", "c5_4site_200k", 10, 10, True, False)):
+            print(f"[bench] extra workload {key}", file=sys.stderr, flush=True)
+            extra[key] = measure_extra(md, W, torch, name, ev, st, adj, hs)
         out["workloads"] = extra
 
     # ---- oracle rows: FP32 errors on a sample and the CPU baseline ----

@@ -56,6 +56,11 @@ enum {
 /* md_model_create flags */
 #define MD_LJ_SHIFT 0x1u /* LJTS: subtract u_ab(r_c) from every LJ site pair inside the cutoff */
 #define MD_CHECK 0x2u    /* validate inputs on the device and sync after every call */
+#define MD_HALF_SHELL 0x4u /* single-site models: evaluate each molecule pair once (Newton's third
+                              law, Fig. 1) with exact partner sums, as multi-site models always do.
+                              Faster for strongly uneven cell occupancy (a vapour-liquid slab),
+                              slower for homogeneous fluids; results differ from the default
+                              kernel by rounding only.  No effect on multi-site models. */
 
 /* precision argument */
 #define MD_FP64 0 /* all pair arithmetic and accumulation in FP64 */
@@ -123,7 +128,7 @@ typedef struct {
  * cutoff.  eps_rf: reaction-field permittivity, INFINITY allowed, applied to dipole-dipole site
  * pairs of molecule pairs inside the cutoff as -kappa mu_a.mu_b / r_c^3 with
  * kappa = 2 (eps_rf - 1) / (2 eps_rf + 1) (kappa = 1 at infinity).  flags: MD_LJ_SHIFT,
- * MD_CHECK.  *out receives the model (owned by the caller, free with md_model_destroy).
+ * MD_CHECK, MD_HALF_SHELL.  *out receives the model (owned by the caller, free with md_model_destroy).
  * Allocates device memory on the current device.  Errors: MD_EINVAL, MD_ECOMP, MD_ENONFINITE,
  * MD_ENOMEM, MD_EHIP. */
 int md_model_create(const md_component_desc *comps, int32_t ncomp, const double *xi, const double *eta, double rc,

@@ -124,7 +124,7 @@ int md_model_create(const md_component_desc *comps, int32_t ncomp, const double 
   if (!std::isfinite(rc)) return set_error(MD_ENONFINITE, "md_model_create: r_c not finite");
   if (!(rc > 0.0)) return set_error(MD_EINVAL, "md_model_create: r_c <= 0");
   if (std::isnan(eps_rf) || !(eps_rf > 0.0)) return set_error(MD_EINVAL, "md_model_create: eps_rf must be > 0");
-  if (flags & ~(MD_LJ_SHIFT | MD_CHECK)) return set_error(MD_EINVAL, "md_model_create: unknown flag");
+  if (flags & ~(MD_LJ_SHIFT | MD_CHECK | MD_HALF_SHELL)) return set_error(MD_EINVAL, "md_model_create: unknown flag");
   md_model tmp;
   ModelDev &h = tmp.host;
   std::memset(&h, 0, sizeof h);
@@ -255,8 +255,8 @@ int md_model_create(const md_component_desc *comps, int32_t ncomp, const double 
       (rcode = check_hip(hipMemset(m->status, 0, sizeof(int32_t)), "hipMemset(status)")) ||
       (rcode = dalloc((void **)&m->red2, sizeof(double) * 256 * 256, "reduction")) ||
       (rcode = dalloc((void **)&m->uw, sizeof(double) * 64, "sums")) ||
-      (!m->single_site && ((rcode = dalloc((void **)&m->bad, sizeof(unsigned long long) * (1 + BAD_CAP), "fix-up list")) ||
-                           (rcode = check_hip(hipMemset(m->bad, 0, sizeof(unsigned long long)), "hipMemset(fix-up list)"))))) {
+      (rcode = dalloc((void **)&m->bad, sizeof(unsigned long long) * (1 + BAD_CAP), "fix-up list")) ||
+      (rcode = check_hip(hipMemset(m->bad, 0, sizeof(unsigned long long)), "hipMemset(fix-up list)"))) {
     md_model_destroy(m);
     return rcode;
   }
@@ -400,9 +400,12 @@ static int forces_impl(md_model *m, const md_cells *c, int precision, double *fo
                  nb * PARTIAL_COLS + KIN_COLS * ((3 * c->N + 255) / 256 + (c->N + 255) / 256), "partial")))
     return rc;
   const int nq = (u_mol || w_mol || nnb_mol) ? 9 : 6;
-  // force/torque rows in the path's precision, then the FP64 u, w, count rows (nq = 9)
-  const int64_t ft_doubles = (int64_t)N3_ROWS * c->N * 6 * (precision == MD_FP32 ? 4 : 8) / 8;
-  if (!m->single_site &&
+  // half-shell rows: force (and torque) in the path's precision, then (256-byte aligned) the FP64
+  // u, w, count rows when nq = 9
+  const bool half_shell = !m->single_site || (m->flags & MD_HALF_SHELL);
+  const int64_t ft_bytes = (int64_t)N3_ROWS * c->N * (m->single_site ? 3 : 6) * (precision == MD_FP32 ? 4 : 8);
+  const int64_t ft_doubles = (ft_bytes + 255) / 256 * 32;
+  if (half_shell &&
       (rc = grow(m->rows, m->cap_rows, ft_doubles + (nq > 6 ? (int64_t)N3_ROWS * c->N * 3 : 0), "pair rows")))
     return rc;
   PairOut o{force, torque, u_mol, w_mol, nnb_mol, m->partial, m->rows, m->rows + ft_doubles, c->N, nq, m->status,
@@ -489,7 +492,8 @@ int md_long_range_correction(const md_component_desc *comps, int32_t ncomp, cons
   if (ncomp > MD_MAX_COMP) return set_error(MD_ECOMP, "md_long_range_correction: ncomp exceeds MD_MAX_COMP");
   if (!std::isfinite(rc)) return set_error(MD_ENONFINITE, "md_long_range_correction: r_c not finite");
   if (!(rc > 0.0)) return set_error(MD_EINVAL, "md_long_range_correction: r_c <= 0");
-  if (flags & ~(MD_LJ_SHIFT | MD_CHECK)) return set_error(MD_EINVAL, "md_long_range_correction: unknown flag");
+  if (flags & ~(MD_LJ_SHIFT | MD_CHECK | MD_HALF_SHELL))
+    return set_error(MD_EINVAL, "md_long_range_correction: unknown flag");
   double V = 1.0;
   for (int k = 0; k < 3; ++k) {
     if (!std::isfinite(box[k])) return set_error(MD_ENONFINITE, "md_long_range_correction: box not finite");

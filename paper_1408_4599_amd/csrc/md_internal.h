@@ -70,10 +70,11 @@ struct PairOut {
   double *force, *torque, *u_mol, *w_mol;
   int32_t *nnb_mol;
   double *partial;  // [gridDim.x][PARTIAL_COLS]
-  // half-shell multi-site kernel: per-molecule rows in sorted order, row 0 the molecule's own
-  // sums, row 1 + k the partner sums from the cell at half-stencil entry -k, summed by the
-  // gather: rows [N3_ROWS][N][6] force and torque in the precision of the path (float or double),
-  // rows_uw [N3_ROWS][N][3] u, w and the partner count in FP64 when nq = 9 (else nq = 6)
+  // half-shell kernel: per-molecule rows in sorted order, row 0 the molecule's own sums, row
+  // 1 + k the partner sums from the cell at half-stencil entry -k, summed by the gather:
+  // rows [N3_ROWS][N][NT] force (NT = 3, one LJ site at the centre) or force and torque (NT = 6)
+  // in the precision of the path (float or double), rows_uw [N3_ROWS][N][3] u, w and the partner
+  // count in FP64 when nq = 9 (per-molecule outputs wanted; else nq = 6)
   void *rows;
   double *rows_uw;
   int64_t n;

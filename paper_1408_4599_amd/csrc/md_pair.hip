@@ -665,8 +665,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
   constexpr int LCAP = 32;
   static_assert(CAP <= 256, "list entries are bytes");
   __shared__ double jp[CAP * 3 + 48];  // slack: the walk reads up to 2 NS - 1 slots past the window
-  __shared__ double jl[CAP][SL * 3];   // LJ site offsets (FP64)
-  __shared__ R jv[CAP][NE * 3];        // electrostatic site offsets and axes
+  constexpr int CAPV = SL == 1 && NV == 1 && !MIX ? 1 : CAP;  // no site vectors for a centre-only site
+  __shared__ double jl[CAPV][SL * 3];  // LJ site offsets (FP64)
+  __shared__ R jv[CAPV][NE * 3];       // electrostatic site offsets and axes
   __shared__ int jc_[MIX ? CAP : 1];
   __shared__ unsigned char lists[W][LCAP * 64];
   __shared__ int scnts[W][64];
@@ -679,16 +680,21 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
   // asked for; for R = double the 32-bit high words of the force and torque follow, [6][CAP]
   extern __shared__ unsigned long long jacc[];
   constexpr bool F64 = sizeof(R) == 8;
+  // one LJ site at the centre (single-site model): no site vectors, no torques, NT = 3 partner
+  // quantities (force) instead of 6 (force, torque)
+  constexpr bool COM = SL == 1 && SC + SD + SQ == 0 && !MIX;
+  constexpr int NT = COM ? 3 : 6;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   unsigned char *list = lists[wave];
   int *scnt = scnts[wave];
   const int cell = xcd_remap(blockIdx.x, gridDim.x);
   const bool full = o.nq > 6;
-  const int nwords = 6 + (full ? 4 : 0);
+  const int nwords = NT + (full ? 4 : 0);
   int *const jhi = (int *)(jacc + nwords * CAP);
   R *const rft = (R *)o.rows;
   const double shift0 = md->shift_sum[0][0];
+  const LJPair lj0 = md->lj[0][0][0][0];
   double acc5[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (cell < c.ncell) {
     const int hs = c.cell_start[cell];
@@ -700,7 +706,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
       for (int g = tid; g < M; g += 64 * W) {
         const int k = find_nb(nb.off, g);
         const int64_t ent = (int64_t)(1 + k) * o.n + nb.start[k] + (g - nb.off[k]);
-        for (int q = 0; q < 6; ++q) rft[6 * ent + q] = (R)0;
+        for (int q = 0; q < NT; ++q) rft[NT * ent + q] = (R)0;
         if (full)
           for (int q = 0; q < 3; ++q) o.rows_uw[3 * ent + q] = 0.0;
       }
@@ -725,11 +731,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
         const int sidx = hs + (hc > 0 ? iloc : 0);
         if (act) xi = c.sx[sidx], yi = c.sy[sidx], zi = c.sz[sidx];
         if (MIX) ci = c.scomp[sidx];
-        const double *v = c.svec + (int64_t)sidx * NV * 3;
+        if constexpr (!COM) {
+          const double *v = c.svec + (int64_t)sidx * NV * 3;
 #pragma unroll
-        for (int k = 0; k < NV; ++k) vi[k][0] = (R)v[3 * k], vi[k][1] = (R)v[3 * k + 1], vi[k][2] = (R)v[3 * k + 2];
+          for (int k = 0; k < NV; ++k) vi[k][0] = (R)v[3 * k], vi[k][1] = (R)v[3 * k + 1], vi[k][2] = (R)v[3 * k + 2];
 #pragma unroll
-        for (int k = 0; k < SL; ++k) vil[k][0] = v[3 * k], vil[k][1] = v[3 * k + 1], vil[k][2] = v[3 * k + 2];
+          for (int k = 0; k < SL; ++k) vil[k][0] = v[3 * k], vil[k][1] = v[3 * k + 1], vil[k][2] = v[3 * k + 2];
+        }
       }
       double fx = 0.0, fy = 0.0, fz = 0.0, tx = 0.0, ty = 0.0, tz = 0.0, uu = 0.0, wx = 0.0, wy = 0.0, wz = 0.0;
       double ush = 0.0;  // LJTS shifts of the interacting molecule pairs (mixtures)
@@ -763,13 +771,30 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
               un = list[li];
             }
             const double dx = xi - jp[3 * u], dy = yi - jp[3 * u + 1], dz = zi - jp[3 * u + 2];
-            PairAcc<R> acc{{0, 0, 0}, {0, 0, 0}, 0};
             const int cj = MIX ? jc_[u] : 0;
-            mol_pair<SL, SC, SD, SQ, MIX, R>(md, ci, cj, vil, vi, jl[u], jv[u], dx, dy, dz, acc);
-            addto(fx, acc.F[0]), addto(fy, acc.F[1]), addto(fz, acc.F[2]);
-            addto(tx, acc.T[0]), addto(ty, acc.T[1]), addto(tz, acc.T[2]);
-            addto(uu, acc.u);
-            const double F0 = acc.F[0], F1 = acc.F[1], F2 = acc.F[2];
+            double F0, F1, F2, T0 = 0.0, T1 = 0.0, T2 = 0.0, up;
+            if constexpr (COM) {
+              // LJ between the centres: the separation is the COM separation, in FP64 throughout
+              const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+              const double ir2d = rcp_fp64_from<R>(r2);
+              const double s2d = lj0.sig2 * ir2d;
+              const double s6d = s2d * s2d * s2d;
+              up = (lj0.eps4 * s6d) * (s6d - 1.0);
+              const double fs = (lj0.eps24 * ir2d) * (s6d * fma(2.0, s6d, -1.0));
+              F0 = fs * dx, F1 = fs * dy, F2 = fs * dz;
+              fx += F0, fy += F1, fz += F2;
+            } else {
+              PairAcc<R> acc{{0, 0, 0}, {0, 0, 0}, 0};
+              mol_pair<SL, SC, SD, SQ, MIX, R>(md, ci, cj, vil, vi, jl[u], jv[u], dx, dy, dz, acc);
+              addto(fx, acc.F[0]), addto(fy, acc.F[1]), addto(fz, acc.F[2]);
+              addto(tx, acc.T[0]), addto(ty, acc.T[1]), addto(tz, acc.T[2]);
+              F0 = acc.F[0], F1 = acc.F[1], F2 = acc.F[2];
+              T0 = -(double)acc.T[0] - fma(dy, F2, -(dz * F1));  // partner: -tau - d x F
+              T1 = -(double)acc.T[1] - fma(dz, F0, -(dx * F2));
+              T2 = -(double)acc.T[2] - fma(dx, F1, -(dy * F0));
+              up = acc.u;
+            }
+            uu += up;
             const double dw = fma(dz, F2, fma(dy, F1, dx * F0));
             wx = fma(dx, F0, wx);
             wy = fma(dy, F1, wy);
@@ -777,20 +802,16 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
             const double sh = MIX ? md->shift_sum[ci][cj] : shift0;
             if (MIX) ush += sh;
             nn += 1;
-            // partner: -F and -tau - d x F
-            const double T0 = -(double)acc.T[0] - fma(dy, F2, -(dz * F1));
-            const double T1 = -(double)acc.T[1] - fma(dz, F0, -(dx * F2));
-            const double T2 = -(double)acc.T[2] - fma(dx, F1, -(dy * F0));
-            const double pv[6] = {-F0, -F1, -F2, T0, T1, T2};
+            const double pv[6] = {-F0, -F1, -F2, T0, T1, T2};  // the partner's force and torque
             bool ok = true;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
+            for (int q = 0; q < NT; ++q) {
               if constexpr (F64) ok &= fx2_add(&jacc[q * CAP + u], &jhi[q * CAP + u], pv[q]);
               else ok &= fx1_add(&jacc[q * CAP + u], pv[q]);
             }
             if (full) {
-              ok &= fx_add(&jacc[6 * CAP + u], &jacc[7 * CAP + u], 0.5 * (acc.u - sh));
-              ok &= fx_add(&jacc[8 * CAP + u], &jacc[9 * CAP + u], 0.5 * dw);
+              ok &= fx_add(&jacc[NT * CAP + u], &jacc[(NT + 1) * CAP + u], 0.5 * (up - sh));
+              ok &= fx_add(&jacc[(NT + 2) * CAP + u], &jacc[(NT + 3) * CAP + u], 0.5 * dw);
             }
             if (!ok) jbad[u] = 1;
             atomicAdd(&jn[u], 1u);
@@ -812,14 +833,16 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
           jp[3 * t + 1] = c.sy[src] + nb.sh[k][1];
           jp[3 * t + 2] = c.sz[src] + nb.sh[k][2];
           if (MIX) jc_[t] = c.scomp[src];  // written (clamped to [0, ncomp)) by the gather
-          const double *v = c.svec + (int64_t)src * NV * 3;
+          if constexpr (!COM) {
+            const double *v = c.svec + (int64_t)src * NV * 3;
 #pragma unroll
-          for (int q = 0; q < SL * 3; ++q) jl[t][q] = v[q];
+            for (int q = 0; q < SL * 3; ++q) jl[t][q] = v[q];
 #pragma unroll
-          for (int q = SL * 3; q < NV * 3; ++q) jv[t][q - SL * 3] = (R)v[q];
+            for (int q = SL * 3; q < NV * 3; ++q) jv[t][q - SL * 3] = (R)v[q];
+          }
           for (int q = 0; q < nwords; ++q) jacc[q * CAP + t] = 0ull;
           if constexpr (F64)
-            for (int q = 0; q < 6; ++q) jhi[q * CAP + t] = 0;
+            for (int q = 0; q < NT; ++q) jhi[q * CAP + t] = 0;
           jn[t] = 0u;
           jbad[t] = 0;
         }
@@ -859,15 +882,15 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
             else atomicOr(o.status, MD_DEV_RANGE);
           }
 #pragma unroll 1
-          for (int q = 0; q < o.nq; ++q) {
-            const int w = q < 6 ? q : 6 + 2 * (q - 6);  // first word of quantity q
-            const double v = q == 8   ? (double)K
-                             : bad    ? __builtin_nan("")
-                             : q >= 6 ? fx_value(jacc[w * CAP + t], jacc[(w + 1) * CAP + t], K)
-                             : F64    ? fx2_value(jacc[w * CAP + t], jhi[(q < 6 ? q : 0) * CAP + t], K)
-                                      : fx1_value(jacc[w * CAP + t], K);
-            if (q < 6) rft[6 * ent + q] = ic == 0 ? (R)v : (R)((double)rft[6 * ent + q] + v);
-            else o.rows_uw[3 * ent + q - 6] = ic == 0 ? v : o.rows_uw[3 * ent + q - 6] + v;
+          for (int q = 0; q < NT + (full ? 3 : 0); ++q) {
+            const int w = q < NT ? q : NT + 2 * (q - NT);  // first word of quantity q
+            const double v = q == NT + 2 ? (double)K
+                             : bad       ? __builtin_nan("")
+                             : q >= NT   ? fx_value(jacc[w * CAP + t], jacc[(w + 1) * CAP + t], K)
+                             : F64       ? fx2_value(jacc[w * CAP + t], jhi[(q < NT ? q : 0) * CAP + t], K)
+                                         : fx1_value(jacc[w * CAP + t], K);
+            if (q < NT) rft[NT * ent + q] = ic == 0 ? (R)v : (R)((double)rft[NT * ent + q] + v);
+            else o.rows_uw[3 * ent + q - NT] = ic == 0 ? v : o.rows_uw[3 * ent + q - NT] + v;
           }
         }
       }
@@ -885,8 +908,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
               dn += n0;
       }
       if (lane < hc) {
-        R *row = rft + 6 * (int64_t)(hs + iloc);  // row 0: the molecule's own sums
-        row[0] = (R)fx, row[1] = (R)fy, row[2] = (R)fz, row[3] = (R)tx, row[4] = (R)ty, row[5] = (R)tz;
+        R *row = rft + NT * (int64_t)(hs + iloc);  // row 0: the molecule's own sums
+        row[0] = (R)fx, row[1] = (R)fy, row[2] = (R)fz;
+        if constexpr (!COM) row[3] = (R)tx, row[4] = (R)ty, row[5] = (R)tz;
         if (full) {
           double *ru = o.rows_uw + 3 * (int64_t)(hs + iloc);
           ru[0] = 0.5 * uu, ru[1] = 0.5 * (wx + wy + wz), ru[2] = dn;
@@ -910,6 +934,8 @@ __global__ __launch_bounds__(64) void k_pair_fixup(CellsDev c, const ModelDev *_
                                                    PairOut o) {
   constexpr int NV = Slots<SL, SC, SD, SQ>::nv;
   constexpr int NE = NV - SL > 0 ? NV - SL : 1;
+  constexpr bool COM = SL == 1 && SC + SD + SQ == 0 && !MIX;
+  constexpr int NT = COM ? 3 : 6;
   const unsigned long long cnt = min(o.bad[0], (unsigned long long)BAD_CAP);
   const bool full = o.nq > 6;
   const int lane = threadIdx.x;
@@ -938,7 +964,7 @@ __global__ __launch_bounds__(64) void k_pair_fixup(CellsDev c, const ModelDev *_
     const double jx = c.sx[src] + shx, jy = c.sy[src] + shy, jz = c.sz[src] + shz;
     double jl[SL * 3];
     R jv[NE * 3];
-    {
+    if constexpr (!COM) {
       const double *v = c.svec + src * NV * 3;
 #pragma unroll
       for (int q = 0; q < SL * 3; ++q) jl[q] = v[q];
@@ -955,7 +981,18 @@ __global__ __launch_bounds__(64) void k_pair_fixup(CellsDev c, const ModelDev *_
       if (i < an && !(k == 0 && src - as <= i)) {
         const int sidx = as + i;
         const double dx = c.sx[sidx] - jx, dy = c.sy[sidx] - jy, dz = c.sz[sidx] - jz;
-        if (fma(dz, dz, fma(dy, dy, dx * dx)) < rc2) {
+        if (COM && fma(dz, dz, fma(dy, dy, dx * dx)) < rc2) {
+          const LJPair &p = md->lj[0][0][0][0];
+          const double ir2d = rcp_fp64_from<R>(fma(dz, dz, fma(dy, dy, dx * dx)));
+          const double s2d = p.sig2 * ir2d;
+          const double s6d = s2d * s2d * s2d;
+          const double fs = (p.eps24 * ir2d) * (s6d * fma(2.0, s6d, -1.0));
+          const double F0 = fs * dx, F1 = fs * dy, F2 = fs * dz;
+          v[0] = -F0, v[1] = -F1, v[2] = -F2;
+          v[6] = 0.5 * ((p.eps4 * s6d) * (s6d - 1.0) - md->shift_sum[0][0]);
+          v[7] = 0.5 * fma(dz, F2, fma(dy, F1, dx * F0));
+          v[8] = 1.0;
+        } else if (!COM && fma(dz, dz, fma(dy, dy, dx * dx)) < rc2) {
           R vi[NV][3];
           double vil[SL][3];
           const double *w = c.svec + (int64_t)sidx * NV * 3;
@@ -984,8 +1021,8 @@ __global__ __launch_bounds__(64) void k_pair_fixup(CellsDev c, const ModelDev *_
       }
     }
     if (lane == 0) {
-      R *row = (R *)o.rows + 6 * ent;
-      for (int q = 0; q < 6; ++q) row[q] = (R)sum[q];
+      R *row = (R *)o.rows + NT * ent;
+      for (int q = 0; q < NT; ++q) row[q] = (R)sum[q];
       if (full) o.rows_uw[3 * ent] = sum[6], o.rows_uw[3 * ent + 1] = sum[7], o.rows_uw[3 * ent + 2] = sum[8];
     }
   }
@@ -993,7 +1030,7 @@ __global__ __launch_bounds__(64) void k_pair_fixup(CellsDev c, const ModelDev *_
 
 // Sum of the N3_ROWS rows of every molecule and quantity in row order (in FP64), written in the
 // caller's molecule order (thread per molecule and quantity; row reads coalesced).
-template <typename R, int NQ>
+template <typename R, int NT, int NQ>
 __global__ __launch_bounds__(256) void k_pair_gather(const int32_t *__restrict__ perm, PairOut o) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) o.bad[0] = 0ull;  // the fix-up has run
@@ -1001,24 +1038,26 @@ __global__ __launch_bounds__(256) void k_pair_gather(const int32_t *__restrict__
   const int64_t s = t / NQ;
   const int q = (int)(t - s * NQ);
   double v;
-  if (q < 6) {
-    const R *rows = (const R *)o.rows + 6 * s + q;
+  if (q < NT) {
+    const R *rows = (const R *)o.rows + NT * s + q;
     v = (double)rows[0];
 #pragma unroll
-    for (int r = 1; r < N3_ROWS; ++r) v += (double)rows[r * 6 * o.n];
+    for (int r = 1; r < N3_ROWS; ++r) v += (double)rows[r * NT * o.n];
   } else {
-    const double *rows = o.rows_uw + 3 * s + q - 6;
+    const double *rows = o.rows_uw + 3 * s + q - NT;
     v = rows[0];
 #pragma unroll
     for (int r = 1; r < N3_ROWS; ++r) v += rows[r * 3 * o.n];
   }
   const int64_t orig = perm[s];
-  if (q < 3) o.force[3 * orig + q] = v;
-  else if (q < 6) {
+  if (q < 3) {
+    o.force[3 * orig + q] = v;
+    if (NT == 3 && o.torque) o.torque[3 * orig + q] = 0.0;  // a centre-only site has no torque
+  } else if (q < NT) {
     if (o.torque) o.torque[3 * orig + q - 3] = v;
-  } else if (q == 6) {
+  } else if (q == NT) {
     if (o.u_mol) o.u_mol[orig] = v;
-  } else if (q == 7) {
+  } else if (q == NT + 1) {
     if (o.w_mol) o.w_mol[orig] = v;
   } else if (o.nnb_mol) {
     o.nnb_mol[orig] = (int32_t)v;
@@ -1105,7 +1144,9 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double *red2
 // gather then forms every molecule's results from its rows.
 template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP1, int CAP4, int WPE>
 int launch_ms(const CellsDev &cd, const md_model *m, const PairOut &o, int64_t nb, double mean, hipStream_t s) {
-  const size_t per_slot = (size_t)(6 + (o.nq > 6 ? 4 : 0)) * sizeof(unsigned long long) + (sizeof(R) == 8 ? 6 * sizeof(int) : 0);
+  constexpr int NT = SL == 1 && SC + SD + SQ == 0 && !MIX ? 3 : 6;  // partner force (and torque) quantities
+  const bool full = o.nq > 6;
+  const size_t per_slot = (size_t)(NT + (full ? 4 : 0)) * sizeof(unsigned long long) + (sizeof(R) == 8 ? NT * sizeof(int) : 0);
   if (mean >= 16.0)
     k_pair_ms<R, SL, SC, SD, SQ, MIX, CAP4, 4, WPE>
         <<<(unsigned)nb, 256, per_slot * CAP4, s>>>(cd, m->dev, m->host.rc2, o);
@@ -1116,9 +1157,9 @@ int launch_ms(const CellsDev &cd, const md_model *m, const PairOut &o, int64_t n
   if (rc || o.n == 0) return rc;
   k_pair_fixup<R, SL, SC, SD, SQ, MIX><<<256, 64, 0, s>>>(cd, m->dev, m->host.rc2, o);
   if ((rc = check_hip(hipGetLastError(), "k_pair_fixup"))) return rc;
-  const unsigned gb = (unsigned)((o.n * o.nq + 255) / 256);
-  if (o.nq > 6) k_pair_gather<R, 9><<<gb, 256, 0, s>>>(cd.perm, o);
-  else k_pair_gather<R, 6><<<gb, 256, 0, s>>>(cd.perm, o);
+  const unsigned gb = (unsigned)((o.n * (NT + (full ? 3 : 0)) + 255) / 256);
+  if (full) k_pair_gather<R, NT, NT + 3><<<gb, 256, 0, s>>>(cd.perm, o);
+  else k_pair_gather<R, NT, NT><<<gb, 256, 0, s>>>(cd.perm, o);
   return check_hip(hipGetLastError(), "k_pair_gather");
 }
 
@@ -1144,6 +1185,11 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
   const int64_t nb = pair_blocks(c->ncell);
   *nblocks = nb;
   const bool f32 = precision == MD_FP32;
+  if (m->single_site && (m->flags & MD_HALF_SHELL)) {  // the half-shell kernel, centre-only shape
+    const double mean = (double)c->N / (double)c->ncell;
+    return f32 ? launch_ms<float, 1, 0, 0, 0, false, 96, 256, 3>(cd, m, o, nb, mean, s)
+               : launch_ms<double, 1, 0, 0, 0, false, 96, 256, 3>(cd, m, o, nb, mean, s);
+  }
   if (m->single_site) {
     const LJPair p = m->host.lj[0][0][0][0];
     int cap = std::max(lj1_tile_cap(c->N, c->ncell), 256 * 8 / 3 + 1);

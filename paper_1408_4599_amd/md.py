@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmdcell.so")
 
 MD_OK, MD_EINVAL, MD_EBOX, MD_ECOMP, MD_ENONFINITE, MD_EHIP, MD_ENOMEM, MD_EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
-MD_LJ_SHIFT, MD_CHECK = 0x1, 0x2
+MD_LJ_SHIFT, MD_CHECK, MD_HALF_SHELL = 0x1, 0x2, 0x4
 MD_FP64, MD_FP32 = 0, 1
 # device status word bits (Model.status)
 MD_DEV_NONFINITE, MD_DEV_COMP, MD_DEV_QUAT, MD_DEV_CAPACITY, MD_DEV_RANGE = 0x1, 0x2, 0x4, 0x8, 0x10
@@ -175,13 +175,15 @@ def long_range_correction(model: dict, counts, box):
 
 class Model:
     """A molecule model (component site tables, mixing, cutoff, reaction field) on the device.
-    Built from the model dictionaries of ``workloads``."""
+    Built from the model dictionaries of ``workloads``.  ``half_shell`` selects the half-shell
+    pair kernel for a single-site model (MD_HALF_SHELL)."""
 
-    def __init__(self, model: dict, check: bool = False):
+    def __init__(self, model: dict, check: bool = False, half_shell: bool = False):
         comps = model["components"]
         nc = len(comps)
         descs, self._keep, xi, eta = _component_descs(model)
-        flags = (MD_LJ_SHIFT if model.get("lj_shift") else 0) | (MD_CHECK if check else 0)
+        flags = ((MD_LJ_SHIFT if model.get("lj_shift") else 0) | (MD_CHECK if check else 0) |
+                 (MD_HALF_SHELL if half_shell else 0))
         h = ctypes.c_void_p()
         _check(lib().md_model_create(descs, nc, None if xi is None else xi.ctypes.data_as(_dp),
                                      None if eta is None else eta.ctypes.data_as(_dp), float(model["rc"]),

@@ -121,3 +121,63 @@ def test_fixup_list_overflow_sets_status(md):
     print(f"status {st:#x}, molecules with a NaN force {int(bad.sum())} of {len(pos)}", flush=True)
     assert st & md.MD_DEV_RANGE
     assert 0 < bad.sum() < len(pos)
+
+
+# ---------------------------------------------------------------- single-site models, MD_HALF_SHELL
+from tests.test_gpu_parity import _force_cfg  # noqa: E402
+
+LJ_CASES = ["c1_ljts_4000", "c3_small", "gas_ragged", "dense_lj", "one_cell"]
+
+
+@pytest.mark.parametrize("name", LJ_CASES)
+def test_single_site_half_shell_matches_oracle(md, oracle, name):
+    """MD_HALF_SHELL on single-site LJ fluids (homogeneous, the slab, a ragged gas, dense cells,
+    one overfull cell): pair set bit for bit, FP64 within 1e-11, FP32 within the stated errors,
+    zero torques."""
+    cfg = _force_cfg(name)
+    ref = oracle.rows(cfg["model"], cfg["pos"], cfg["quat"], cfg["comp"], cfg["box"])
+    U = ref["u"].sum()
+    for prec, fbar, ubar in (("fp64", 1e-11, 1e-12), ("fp32", 1e-5, 1e-9)):
+        got, m, _ = run_forces(md, cfg, prec, half_shell=True)
+        np.testing.assert_array_equal(got["nnb"], ref["nnb"])
+        assert got["npairs"] == ref["nnb"].sum() // 2
+        eF, eU = rel_rms(got["force"], ref["F"]), abs(got["U"] - U) / abs(U)
+        print(f"{name} {prec}: eps_F {eF:.2e} eps_U {eU:.2e}", flush=True)
+        assert eF < fbar and eU < ubar
+        assert np.all(got["torque"] == 0.0)
+        if prec == "fp64":
+            assert got["W"] == pytest.approx(ref["w"].sum(), rel=1e-12)
+            assert rel_rms(got["u_mol"], ref["u"]) < 1e-11
+            assert rel_rms(got["w_mol"], ref["w"]) < 1e-11
+        assert m.status() == 0
+
+
+def test_single_site_half_shell_tiny_systems(md, oracle):
+    """N = 2 in a large box and N = 1 through the half-shell kernel."""
+    mdl = W.lj_model(2.5, shift=False)
+    cfg = {"model": mdl, "pos": np.array([[1.0, 1.0, 1.0], [2.2, 1.3, 0.9]]), "quat": None,
+           "comp": np.zeros(2, np.int32), "box": np.array([12.0, 13.0, 14.0])}
+    got, _, _ = run_forces(md, cfg, "fp64", half_shell=True)
+    ref = oracle.forces(mdl, cfg["pos"], None, None, cfg["box"])
+    assert got["npairs"] == 1
+    np.testing.assert_allclose(got["force"], ref["F"], rtol=1e-13)
+    cfg["pos"], cfg["comp"] = cfg["pos"][:1], cfg["comp"][:1]
+    got, _, _ = run_forces(md, cfg, "fp64", half_shell=True)
+    assert got["npairs"] == 0 and np.all(got["force"] == 0) and got["U"] == 0.0
+
+
+def test_single_site_half_shell_steps_follow_the_default_kernel(md):
+    """md_step with MD_HALF_SHELL and with the default kernel from the same state: the same
+    energies to rounding over 20 FP64 steps."""
+    import torch
+    cfg = W.make("c1_ljts_4000")
+    rows = []
+    for hs in (False, True):
+        m = md.Model(cfg["model"], half_shell=hs)
+        cells = md.Cells()
+        pos, vel = dev(cfg["pos"]), dev(cfg["vel"])
+        en = torch.empty((20, 4), dtype=torch.float64, device="cuda")
+        md.step(m, cells, pos, vel, None, None, None, cfg["box"], cfg["dt"], 20, "fp64", en)
+        torch.cuda.synchronize()
+        rows.append(en.cpu().numpy())
+    np.testing.assert_allclose(rows[1], rows[0], rtol=1e-9)
