@@ -445,14 +445,15 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
   }
 }
 
-// Dense cells (mean occupancy >= 16) are shared by four wavefronts, sparser ones take one each.
-template <typename R, int SL, int SC, int SD, int SQ, bool MIX, bool SINGLE, int CAP>
+// Dense cells (mean occupancy >= 16) are shared by four wavefronts with windows of CAP molecules,
+// sparser ones take one wavefront each with windows of CAP1 (smaller LDS per one-wave block).
+template <typename R, int SL, int SC, int SD, int SQ, bool MIX, bool SINGLE, int CAP, int CAP1 = CAP>
 int launch_adj(const CellsDev &cd, const md_model *m, const double *quat, const AdjOut &o, int64_t nb, double mean,
                hipStream_t s) {
   if (mean >= 16.0)
     k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP, 4><<<(unsigned)nb, 256, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
   else
-    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP, 1><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
+    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP1, 1><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
   return check_hip(hipGetLastError(), "k_adjoint");
 }
 
@@ -469,14 +470,14 @@ int launch_adjoint(md_model *m, const md_cells *c, int precision, const AdjOut &
   const Shape &S = m->shape;
   const double mean = (double)c->N / (double)c->ncell;
   if (m->single_site)
-    return f32 ? launch_adj<float, 1, 0, 0, 0, false, true, 256>(cd, m, nullptr, o, nb, mean, s)
-               : launch_adj<double, 1, 0, 0, 0, false, true, 256>(cd, m, nullptr, o, nb, mean, s);
+    return f32 ? launch_adj<float, 1, 0, 0, 0, false, true, 256, 128>(cd, m, nullptr, o, nb, mean, s)
+               : launch_adj<double, 1, 0, 0, 0, false, true, 256, 128>(cd, m, nullptr, o, nb, mean, s);
   if (m->fixed_shape && S.lj == 2 && S.chg == 0 && S.dip == 0 && S.quad == 1)
-    return f32 ? launch_adj<float, 2, 0, 0, 1, false, false, 256>(cd, m, quat, o, nb, mean, s)
-               : launch_adj<double, 2, 0, 0, 1, false, false, 256>(cd, m, quat, o, nb, mean, s);
+    return f32 ? launch_adj<float, 2, 0, 0, 1, false, false, 256, 64>(cd, m, quat, o, nb, mean, s)
+               : launch_adj<double, 2, 0, 0, 1, false, false, 256, 64>(cd, m, quat, o, nb, mean, s);
   if (m->fixed_shape && S.lj == 3 && S.chg == 0 && S.dip == 1 && S.quad == 0)
-    return f32 ? launch_adj<float, 3, 0, 1, 0, false, false, 256>(cd, m, quat, o, nb, mean, s)
-               : launch_adj<double, 3, 0, 1, 0, false, false, 256>(cd, m, quat, o, nb, mean, s);
+    return f32 ? launch_adj<float, 3, 0, 1, 0, false, false, 256, 64>(cd, m, quat, o, nb, mean, s)
+               : launch_adj<double, 3, 0, 1, 0, false, false, 256, 64>(cd, m, quat, o, nb, mean, s);
   return f32 ? launch_adj<float, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, false, 64>(cd, m, quat, o, nb,
                                                                                                     mean, s)
              : launch_adj<double, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, false, 64>(cd, m, quat, o, nb,

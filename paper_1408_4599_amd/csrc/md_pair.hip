@@ -642,8 +642,8 @@ __device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci
 // One block of W wavefronts per home cell, half shell (Newton's third law, Fig. 1): the home cell
 // and the 13 forward neighbours are staged through LDS in windows of CAP molecules shared by the
 // block (COM position in FP64, LJ site offsets in FP64, electrostatic site vectors in R, component
-// id), home cell first; home molecule i pairs with staged molecule g when g > i (every pair of the
-// home cell once, every forward molecule).  The home molecules are split evenly over the
+// id; the COM alone for a single-site model), home cell first; home molecule i pairs with staged
+// molecule g when g > i (every pair of the home cell once, every forward molecule).  The home molecules are split evenly over the
 // wavefronts, and in a wavefront with n of them lanes are n molecules x NS partner slices
 // (NS = min(8, floor(64 / n))).  Pass 1 runs the exact FP64 COM cutoff test and appends hits
 // (window slots, one byte) to per-lane lists; pass 2 evaluates the listed molecule pairs, the hits
@@ -653,8 +653,7 @@ __device__ __forceinline__ void mol_pair(const ModelDev *__restrict__ md, int ci
 // rotation of both molecules, so the torques about the two centres and d x F sum to zero), plus
 // half of the pair energy and virial when asked for; these go to per-slot LDS sums in exact
 // integer arithmetic (fx1_add on the FP32 path, fx2_add on the FP64 path, fx_add for u, w), which
-// the block writes, once per window, to the partner's row
-// 1 + k (k its half-stencil entry).  Each (row, molecule) is written by exactly one block, also
+// the block writes, once per window, to the partner's row 1 + k (k its half-stencil entry).  Each (row, molecule) is written by exactly one block, also
 // when its home cell is empty.  A home cell with more than 64 W molecules is taken 64 W at a time;
 // later rounds add to the rows of the first.
 template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP, int W, int WPE>
@@ -675,9 +674,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(WPE))) v
   __shared__ double red[W][5];
   __shared__ unsigned jn[CAP];  // partner terms per slot
   __shared__ int jbad[CAP];     // a term of the slot was out of the fixed-point range
-  // partner sums [words][CAP]: force and torque components one 64-bit word each (R = float:
+  // partner sums [words][CAP]: force (and torque) components one 64-bit word each (R = float:
   // fx1_add; R = double: the low words of fx2_add), then u and w two words each (fx_add) when
-  // asked for; for R = double the 32-bit high words of the force and torque follow, [6][CAP]
+  // asked for; for R = double the 32-bit high words of the force (and torque) follow, [NT][CAP]
   extern __shared__ unsigned long long jacc[];
   constexpr bool F64 = sizeof(R) == 8;
   // one LJ site at the centre (single-site model): no site vectors, no torques, NT = 3 partner
