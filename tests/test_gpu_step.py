@@ -93,6 +93,21 @@ def test_step_nve_fp32_energy_conservation(md):
     assert s32 < 1.5 * s64 + 1e-6
 
 
+@pytest.mark.parametrize("name", ["c4_small", "c5_small"])
+def test_step_nve_fp32_energy_conservation_multisite(md, name):
+    """Multi-site models (half shell: partner forces and torques summed in fixed point on the
+    FP32 path) over 200 steps: the total energy, rotation included, stays within the band of the
+    FP64 path."""
+    cfg = W.make(name)
+    *_, e32 = _run_gpu(md, cfg, 200, "fp32")
+    *_, e64 = _run_gpu(md, cfg, 200, "fp64")
+    E32, E64 = e32[:, :3].sum(1), e64[:, :3].sum(1)
+    s32 = np.abs(E32 - E32[0]).max() / abs(E32[0])
+    s64 = np.abs(E64 - E64[0]).max() / abs(E64[0])
+    print(f"{name}: relative energy band fp64 {s64:.2e} fp32 {s32:.2e}", flush=True)
+    assert s32 < 1.5 * s64 + 1e-6
+
+
 def test_step_checkpoint_resume_is_bitwise(md):
     """100 steps equal 50 steps, copy the state out (checkpoint), then 50 more from the copy."""
     cfg = W.make("c4_small")
