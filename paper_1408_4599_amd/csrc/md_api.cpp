@@ -103,7 +103,8 @@ static int sync_check(md_model *m, hipStream_t s) {
     launch_fill_i32(m->status, 1, 0, s);
     (void)hipStreamSynchronize(s);
     return set_error(MD_EDEVICE, "device status word " + std::to_string(st) +
-                                     " (1: non-finite position, 2: component id, 4: non-unit quaternion)");
+                                     " (1: non-finite position, 2: component id, 4: non-unit quaternion, "
+                                     "16: fix-up list full)");
   }
   return MD_OK;
 }
@@ -267,6 +268,14 @@ int md_model_create(const md_component_desc *comps, int32_t ncomp, const double 
 int md_model_destroy(md_model *m) {
   if (!m) return MD_OK;
   for (auto &e : m->events) (void)hipEventDestroy(e.a), (void)hipEventDestroy(e.b);
+  if (m->side) {
+    (void)hipStreamSynchronize(m->side);
+    (void)hipStreamDestroy(m->side);
+  }
+  for (int k = 0; k < 2; ++k) {
+    if (m->ev_leap[k]) (void)hipEventDestroy(m->ev_leap[k]);
+    if (m->ev_red[k]) (void)hipEventDestroy(m->ev_red[k]);
+  }
   dfree(m->dev);
   dfree(m->status);
   dfree(m->partial);
@@ -393,7 +402,7 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
 // together with the leapfrog's kinetic-energy partials, which follow them in m->partial).
 static int forces_impl(md_model *m, const md_cells *c, int precision, double *force, double *torque, double *u_mol,
                        double *w_mol, int32_t *nnb_mol, double *uw, int64_t *npairs, double *erow, hipStream_t s,
-                       bool reduce = true, int64_t *nblocks_out = nullptr) {
+                       bool reduce = true, int64_t *nblocks_out = nullptr, double *partial = nullptr) {
   const int64_t nb = pair_blocks(c->ncell);
   int rc;
   if ((rc = grow(m->partial, m->cap_partial,
@@ -408,7 +417,8 @@ static int forces_impl(md_model *m, const md_cells *c, int precision, double *fo
   if (half_shell &&
       (rc = grow(m->rows, m->cap_rows, ft_doubles + (nq > 6 ? (int64_t)N3_ROWS * c->N * 3 : 0), "pair rows")))
     return rc;
-  PairOut o{force, torque, u_mol, w_mol, nnb_mol, m->partial, m->rows, m->rows + ft_doubles, c->N, nq, m->status,
+  if (!partial) partial = m->partial;
+  PairOut o{force, torque, u_mol, w_mol, nnb_mol, partial, m->rows, m->rows + ft_doubles, c->N, nq, m->status,
             m->bad};
   int64_t nblocks = 0;
   hipEvent_t ev;
@@ -417,7 +427,7 @@ static int forces_impl(md_model *m, const md_cells *c, int precision, double *fo
   prof_end(m, PROF_PAIR, s, ev);
   if (rc) return rc;
   if (nblocks_out) *nblocks_out = nblocks;
-  return reduce ? launch_reduce_forces(m, nblocks, m->partial, uw, npairs, erow, s) : MD_OK;
+  return reduce ? launch_reduce_forces(m, nblocks, partial, uw, npairs, erow, s) : MD_OK;
 }
 
 int md_forces(md_model *m, const md_cells *c, int precision, double *force, double *torque, double *u_mol,
@@ -449,29 +459,61 @@ int md_step(md_model *m, md_cells *c, double *pos, double *vel, double *quat, do
       return rc;
     m->cap_step = N;
   }
+  const bool nvt = m->T_target > 0.0;
+  // with an energies row and no thermostat, each step's reduction goes to the side stream and
+  // overlaps the next step; the pair and kinetic partial rows then alternate between two slots
+  const bool overlap = energies && !nvt && nsteps > 1;
+  int64_t slot_sz = 0;
   for (int64_t st = 0; st < nsteps; ++st) {
     if ((rc = md_build_cells(m, c, pos, quat, comp, N, box, stream))) return rc;
+    if (overlap && st == 0) {  // the grid is fixed within the call (same box, same cutoff)
+      slot_sz = pair_blocks(c->ncell) * PARTIAL_COLS + KIN_COLS * ((3 * N + 255) / 256 + (N + 255) / 256);
+      if ((rc = grow(m->partial, m->cap_partial, 2 * slot_sz, "partial"))) return rc;
+      if (!m->side && (rc = check_hip(hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking), "hipStreamCreate")))
+        return rc;
+      for (int k = 0; k < 2; ++k)
+        if ((!m->ev_leap[k] && (rc = check_hip(hipEventCreateWithFlags(&m->ev_leap[k], hipEventDisableTiming), "hipEventCreate"))) ||
+            (!m->ev_red[k] && (rc = check_hip(hipEventCreateWithFlags(&m->ev_red[k], hipEventDisableTiming), "hipEventCreate"))))
+          return rc;
+    }
+    const int slot = (int)(st & 1);
+    // partial rows: the slot of this step, or (without overlap) the buffer forces_impl sizes,
+    // read back after the call, which may allocate it
+    double *part = overlap ? m->partial + slot * slot_sz : nullptr;
+    // the reduction of step st - 2 has read this slot
+    if (overlap && st >= 2 && (rc = check_hip(hipStreamWaitEvent(s, m->ev_red[slot], 0), "hipStreamWaitEvent")))
+      return rc;
     double *erow = energies ? energies + 4 * st : nullptr;
     int64_t nbp = 0;
     if ((rc = forces_impl(m, c, precision, m->force, m->single_site ? nullptr : m->torque, nullptr, nullptr, nullptr,
-                          m->uw + 8, nullptr, erow, s, false, &nbp)))
+                          m->uw + 8, nullptr, erow, s, false, &nbp, part)))
       return rc;
+    if (!part) part = m->partial;
     hipEvent_t ev;
     prof_begin(m, PROF_STEP, s, &ev);
-    double *kin = m->partial + nbp * PARTIAL_COLS;  // after the pair partials
+    double *kin = part + nbp * PARTIAL_COLS;  // after the pair partials
     int64_t nkin = 0;
     rc = launch_leapfrog(m, pos, vel, quat, angmom, m->host.ncomp > 1 ? comp : nullptr, N, box, dt, m->force,
                          m->torque, kin, &nkin, s);
     // energies row: U, W from the pair partials and K_trans, K_rot from the leapfrog's, in one
     // reduction (skipped when neither energies nor the thermostat need it); the thermostat then
     // rescales the new half-step velocities from the reduced K(t) and degrees of freedom
-    const bool nvt = m->T_target > 0.0;
-    if (!rc && (erow || nvt)) rc = launch_reduce_forces(m, nbp, m->partial, m->uw + 8, nullptr, erow, s, kin, nkin);
+    if (!rc && overlap) {
+      rc = check_hip(hipEventRecord(m->ev_leap[slot], s), "hipEventRecord");
+      if (!rc) rc = check_hip(hipStreamWaitEvent(m->side, m->ev_leap[slot], 0), "hipStreamWaitEvent");
+      if (!rc) rc = launch_reduce_forces(m, nbp, part, m->uw + 8, nullptr, erow, m->side, kin, nkin);
+      if (!rc) rc = check_hip(hipEventRecord(m->ev_red[slot], m->side), "hipEventRecord");
+    } else if (!rc && (erow || nvt)) {
+      rc = launch_reduce_forces(m, nbp, part, m->uw + 8, nullptr, erow, s, kin, nkin);
+    }
     if (!rc && nvt)
       rc = launch_rescale(m, vel, angmom, m->host.ncomp > 1 ? comp : nullptr, N, m->uw + 13, m->T_target, s);
     prof_end(m, PROF_STEP, s, ev);
     if (rc) return rc;
   }
+  // the caller's stream sees every reduction of this call
+  if (overlap && (rc = check_hip(hipStreamWaitEvent(s, m->ev_red[(nsteps - 1) & 1], 0), "hipStreamWaitEvent")))
+    return rc;
   return sync_check(m, s);
 }
 

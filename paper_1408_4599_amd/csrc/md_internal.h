@@ -136,6 +136,10 @@ struct md_model {
   double *force = nullptr, *torque = nullptr, *uw = nullptr;
   int64_t cap_step = 0;
   double T_target = 0.0;        // velocity-rescaling thermostat (0: NVE)
+  // md_step with an energies row and no thermostat: each step's reduction runs on a side stream
+  // (default priority), overlapping the next step; the partial rows alternate between two slots
+  hipStream_t side = nullptr;
+  hipEvent_t ev_leap[2] = {nullptr, nullptr}, ev_red[2] = {nullptr, nullptr};
   int lds_limit = 0;            // LDS bytes per block on the model's device (queried at first use)
   int lj1_static_lds[2] = {-1, -1};  // static LDS of the single-site pair kernel (FP64, FP32)
   // profiling
