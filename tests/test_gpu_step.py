@@ -121,6 +121,24 @@ def test_step_checkpoint_resume_is_bitwise(md):
 
 
 @pytest.mark.parametrize("name", ["c1_ljts_4000", "c4_small"])
+def test_step_energies_on_the_side_stream_equal_single_steps(md, name):
+    """One call of 6 steps with an energies row reduces each step on the model's side stream,
+    overlapping the next step; six one-step calls reduce on the caller's stream.  Energies rows
+    and final state agree bit for bit."""
+    cfg = W.make(name)
+    a = _run_gpu(md, cfg, 6)
+    m = md.Model(cfg["model"])
+    cells = md.Cells()
+    pos, vel = dev(cfg["pos"]), dev(cfg["vel"])
+    quat, ang = dev(cfg["quat"]), dev(cfg["angmom"])
+    rows = [md.step(m, cells, pos, vel, quat, ang, None, cfg["box"], cfg["dt"], 1, "fp64").cpu().numpy()[0]
+            for _ in range(6)]
+    np.testing.assert_array_equal(np.array(rows), a[4])
+    np.testing.assert_array_equal(pos.cpu().numpy(), a[0])
+    np.testing.assert_array_equal(vel.cpu().numpy(), a[1])
+
+
+@pytest.mark.parametrize("name", ["c1_ljts_4000", "c4_small"])
 def test_step_nvt_without_energies_row_is_bitwise_the_same(md, name):
     """md_step with energies = NULL still reduces K(t) for the thermostat: the final state equals
     the run that also writes the energies row, bit for bit."""
