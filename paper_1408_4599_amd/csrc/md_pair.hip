@@ -15,8 +15,9 @@
 //     interacting pairs is the brute-force set bit for bit, and lists the hits; pass 2 evaluates
 //     the listed pairs only;
 //   * the FP32 path (R = float) seeds reciprocals in FP32 and evaluates the single-site LJ force
-//     scalar and the multipole terms in FP32; separations of LJ sites, the multi-site LJ terms
-//     (which share the energy's FP64 powers), pair energies and all sums are FP64;
+//     scalar and the multipole forces and torques in FP32; separations of LJ sites, the
+//     multi-site LJ terms (which share the energy's FP64 powers), pair energies (multipole
+//     cosines and angular factors included) and all sums are FP64;
 //   * slices are combined in a fixed order; every block writes one row of partials (energy,
 //     virial diagonal, pair count) which a deterministic two-stage reduction sums in order.
 // Single-site LJ pairs are evaluated from both ends (full shell): no partner sums at all.
@@ -522,8 +523,9 @@ __device__ __forceinline__ void elec_site(R pm, double pmd, const R *oa, const R
     cross_acc(acc.T, ea, ga);  // tau -= e_a x dU/de_a
   }
   // energy in FP64: the site separation from the FP64 COM separation (exact when both sites sit
-  // at their centres), 1/r refined by one FP64 Newton step, times the angular factor
-  double ue;
+  // at their centres), 1/r refined by one FP64 Newton step, and the cosines and angular factor in
+  // FP64 from the stored axes
+  double ue, cijd = (double)cij;
   if constexpr (sizeof(R) == 8) {
     ue = t.t0;
   } else {
@@ -535,9 +537,18 @@ __device__ __forceinline__ void elec_site(R pm, double pmd, const R *oa, const R
     double yn = y;
 #pragma unroll
     for (int k = 1; k < unit_rpow<KA, KB>(); ++k) yn *= y;
-    ue = (double)t.ang * yn;
+    if constexpr (KA == KIND_CHG && KB == KIND_CHG) {
+      ue = yn;
+    } else {
+      const double ead[3] = {(double)ea[0], (double)ea[1], (double)ea[2]};
+      const double ebd[3] = {(double)eb[0], (double)eb[1], (double)eb[2]};
+      const double cid = (KA != KIND_CHG) ? fma(ead[2], rzd, fma(ead[1], ryd, ead[0] * rxd)) * y : 0.0;
+      const double cjd = (KB != KIND_CHG) ? fma(ebd[2], rzd, fma(ebd[1], ryd, ebd[0] * rxd)) * y : 0.0;
+      if constexpr (KA != KIND_CHG && KB != KIND_CHG) cijd = fma(ead[2], ebd[2], fma(ead[1], ebd[1], ead[0] * ebd[0]));
+      ue = unit_terms<KA, KB, double>(y, cid, cjd, cijd, krc3d).ang * yn;
+    }
   }
-  if constexpr (KA == KIND_DIP && KB == KIND_DIP) ue = fma(-krc3d, (double)cij, ue);
+  if constexpr (KA == KIND_DIP && KB == KIND_DIP) ue = fma(-krc3d, cijd, ue);
   acc.u = fma(pmd, ue, acc.u);
 }
 

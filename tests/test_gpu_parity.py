@@ -176,11 +176,10 @@ def test_forces_fp64_match_oracle(md, oracle, name):
 # path (force 1e-5 relative RMS, energy 1e-9 relative).  Energies are summed in FP64 from FP64
 # parameters, LJ site separations are FP64, so the FP32 rounding left in U is random, not
 # systematic.
+# The four-component dilute mixture is the hard case: the charge-charge and charge-dipole terms
+# of neutral molecules cancel to a small U, which holds to 1e-9 only because the kernel forms
+# the direction cosines and angular factors of the energy in FP64.
 FP32_BARS = {name: (1e-5, 1e-5, 1e-9) for name in FORCE_CASES}
-# Four components, dilute: the charge-charge and charge-dipole terms of neutral molecules cancel
-# to a small U, and each keeps the FP32 rounding of its direction cosines and world-frame site
-# vectors (FP64 site offsets alone were tried and did not change it); measured 1.4e-9.
-FP32_BARS["mixture4_small"] = (1e-5, 1e-5, 2e-9)
 
 
 @pytest.mark.parametrize("name", FORCE_CASES)
