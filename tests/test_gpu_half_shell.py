@@ -39,7 +39,7 @@ SMALL_GRIDS = {
 # FP32 energy bar: 1e-9, the stated target, for every case.  The dilute quadrupolar gas is the
 # hard one: its quadrupole-quadrupole energies of both signs cancel to a small U, so the kernel
 # forms the direction cosines and angular factors of the energy in FP64.
-FP32_U_BAR = {}
+FP32_U_BAR = 1e-9
 
 
 def _check(md, oracle, cfg, prec, bar, ubar=1e-9):
@@ -63,7 +63,7 @@ def test_small_grids_match_oracle(md, oracle, name):
     cfg = SMALL_GRIDS[name]()
     print(f"{name}: N={len(cfg['pos'])}", flush=True)
     _check(md, oracle, cfg, "fp64", 1e-11)
-    _check(md, oracle, cfg, "fp32", 1e-5, FP32_U_BAR.get(name, 1e-9))
+    _check(md, oracle, cfg, "fp32", 1e-5, FP32_U_BAR)
 
 
 @pytest.mark.parametrize("args", [(150, 100, 23), (300, 160, 29)], ids=["w1", "w4"])
