@@ -69,7 +69,9 @@ enum {
                      accumulation and reductions in FP64 */
 
 /* device status word bits (md_status) */
-#define MD_DEV_NONFINITE 0x1 /* a position was NaN/Inf */
+#define MD_DEV_NONFINITE 0x1 /* a position was NaN/Inf: that molecule is spread into cell
+                                (index mod ncell), takes part in no pair and gets zero force,
+                                torque and energy; the others are evaluated as without it */
 #define MD_DEV_COMP 0x2      /* a component id was outside [0, ncomp) */
 #define MD_DEV_QUAT 0x4      /* | |q|^2 - 1 | > 1e-6 for some molecule */
 #define MD_DEV_CAPACITY 0x8  /* internal capacity exceeded (should not happen) */
@@ -140,6 +142,18 @@ int md_model_destroy(md_model *m);
  * [dq, dx, dy, dz], each dipole [dmu, dx, dy, dz], each quadrupole [dQ, dx, dy, dz]
  * (dx, dy, dz: derivative w.r.t. the body-frame site offset). */
 int64_t md_param_count(const md_model *m);
+
+/* Read (get) or replace (set) the model's differentiable parameters, host [md_param_count(m)]
+ * doubles in the layout of md_param_count and md_forces_adjoint's dparams: the site energies,
+ * sizes, body-frame offsets, charges and dipole / quadrupole moments of Sec. 2's models.  set
+ * re-derives the mixed LJ pair tables (Lorentz-Berthelot with the model's xi / eta) and the LJTS
+ * shifts, then waits for all work on the device (syncs) and uploads the tables; masses, inertia,
+ * site axes, r_c and the reaction field are unchanged.  The site of a single-site model stays at
+ * its centre of mass.  Errors: NULL argument (MD_EINVAL), non-finite value (MD_ENONFINITE), LJ
+ * epsilon or sigma <= 0 or a moved single-site offset (MD_EINVAL; the model is unchanged),
+ * MD_EHIP. */
+int md_model_get_params(const md_model *m, double *params);
+int md_model_set_params(md_model *m, const double *params);
 
 int md_cells_create(md_cells **out);
 int md_cells_destroy(md_cells *c);
@@ -219,7 +233,13 @@ int md_long_range_correction(const md_component_desc *comps, int32_t ncomp, cons
                              double rc, uint32_t flags, const int64_t *counts, const double box[3], double *u_lrc,
                              double *w_lrc);
 
-/* Gradient of gU * U for the built configuration, recomputing every pair (no stored pair list):
+/* Gradient of gU * U for the built configuration, recomputing every pair (no stored pair list).
+ * "The built configuration" is the library-owned copy that the last md_build_cells on `cells`
+ * took of pos and quat (sorted COMs, quaternions and site vectors): the caller may change or free
+ * its own pos / quat arrays after md_build_cells returns.  After md_step, that copy is the
+ * configuration at the start of the last step (before its drift), not the updated arrays; build
+ * again to differentiate the new state. */
+/* Outputs:
  *   dpos    [N][3]  gU dU/dr_i (= -gU F_i)
  *   dquat   [N][4]  gU dU/dq_i with respect to the raw quaternion components (NULL allowed)
  *   dparams [md_param_count(m)] gU dU/d(parameters), layout as md_param_count (NULL allowed)

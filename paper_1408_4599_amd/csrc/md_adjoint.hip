@@ -346,7 +346,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
         orig = c.perm[hs + iloc];
         if (quat)
 #pragma unroll
-          for (int k = 0; k < 4; ++k) q[k] = quat[4 * orig + k];
+          for (int k = 0; k < 4; ++k) q[k] = quat[4 * (int64_t)(hs + iloc) + k];
         double dp[3] = {0.0, 0.0, 0.0};
 #pragma unroll
         for (int a = 0; a < Acc::NSITE; ++a) dp[0] += acc.gs[a][0], dp[1] += acc.gs[a][1], dp[2] += acc.gs[a][2];

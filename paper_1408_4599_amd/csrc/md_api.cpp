@@ -3,7 +3,6 @@
 // HIP kernels of md_cells.hip, md_pair.hip, md_step.hip and md_adjoint.hip.
 
 #include <cmath>
-#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -25,10 +24,8 @@ int check_hip(hipError_t e, const char *what) {
   return set_error(MD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// Device allocation; MDCELL_TEST_FAIL_ALLOC=1 in the environment makes it fail (test hook).
+// Device allocation: MD_ENOMEM when the device is out of memory, MD_EHIP for other failures.
 static int dalloc(void **p, size_t bytes, const char *what) {
-  const char *f = std::getenv("MDCELL_TEST_FAIL_ALLOC");
-  if (f && f[0] == '1') return set_error(MD_ENOMEM, std::string("allocation refused by test hook: ") + what);
   if (bytes == 0) bytes = 8;
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
@@ -107,6 +104,60 @@ static int sync_check(md_model *m, hipStream_t s) {
                                      "16: fix-up list full)");
   }
   return MD_OK;
+}
+
+// Lorentz-Berthelot mixing per LJ site pair (Sec. 2), with the optional LJTS shift u_ab(r_c) and
+// the adjoint's per-pair factors; recomputed whenever the site parameters change.
+static void mix_lj(ModelDev &h) {
+  std::memset(h.lj, 0, sizeof h.lj);
+  std::memset(h.shift_sum, 0, sizeof h.shift_sum);
+  const int ncomp = h.ncomp;
+  for (int A = 0; A < ncomp; ++A)
+    for (int B = 0; B < ncomp; ++B)
+      for (int a = 0; a < h.comp[A].n_lj; ++a)
+        for (int b = 0; b < h.comp[B].n_lj; ++b) {
+          const double eps = h.xi[A][B] * std::sqrt(h.comp[A].lj_eps[a] * h.comp[B].lj_eps[b]);
+          const double sig = h.eta[A][B] * 0.5 * (h.comp[A].lj_sig[a] + h.comp[B].lj_sig[b]);
+          LJPair &p = h.lj[A][B][a][b];
+          p.eps4 = 4.0 * eps;
+          p.eps24 = 24.0 * eps;
+          p.sig2 = sig * sig;
+          p.pe = 0.5 / h.comp[A].lj_eps[a];
+          p.ps = 0.5 * h.eta[A][B] * 4.0 * eps / sig;
+          if (h.lj_shift) {
+            const double c2 = sig * sig / h.rc2;
+            const double c6 = c2 * c2 * c2;
+            p.shift = 4.0 * eps * (c6 * c6 - c6);
+            p.csh = 12.0 * c6 * c6 - 6.0 * c6;
+          } else {
+            p.shift = 0.0;
+            p.csh = 0.0;
+          }
+          h.shift_sum[A][B] += p.shift;
+        }
+}
+
+// Walk the parameter vector in the md_param_count layout; f(value reference, is_lj_magnitude)
+template <typename F> void for_each_param(ModelDev &h, F f) {
+  for (int c = 0; c < h.ncomp; ++c) {
+    CompDev &cd = h.comp[c];
+    for (int a = 0; a < cd.n_lj; ++a) {
+      f(cd.lj_eps[a], true), f(cd.lj_sig[a], true);
+      for (int k = 0; k < 3; ++k) f(cd.lj_pos[a][k], false);
+    }
+    for (int a = 0; a < cd.n_chg; ++a) {
+      f(cd.chg_q[a], false);
+      for (int k = 0; k < 3; ++k) f(cd.chg_pos[a][k], false);
+    }
+    for (int a = 0; a < cd.n_dip; ++a) {
+      f(cd.dip_mu[a], false);
+      for (int k = 0; k < 3; ++k) f(cd.dip_pos[a][k], false);
+    }
+    for (int a = 0; a < cd.n_quad; ++a) {
+      f(cd.quad_Q[a], false);
+      for (int k = 0; k < 3; ++k) f(cd.quad_pos[a][k], false);
+    }
+  }
 }
 
 }  // namespace mdcell
@@ -203,30 +254,7 @@ int md_model_create(const md_component_desc *comps, int32_t ncomp, const double 
       if (!(x > 0.0) || !(e > 0.0)) return set_error(MD_EINVAL, "md_model_create: xi/eta must be > 0");
       h.xi[a][b] = x, h.eta[a][b] = e;
     }
-  // Lorentz-Berthelot mixing per LJ site pair, with the optional LJTS shift u_ab(r_c).
-  for (int A = 0; A < ncomp; ++A)
-    for (int B = 0; B < ncomp; ++B)
-      for (int a = 0; a < h.comp[A].n_lj; ++a)
-        for (int b = 0; b < h.comp[B].n_lj; ++b) {
-          const double eps = h.xi[A][B] * std::sqrt(h.comp[A].lj_eps[a] * h.comp[B].lj_eps[b]);
-          const double sig = h.eta[A][B] * 0.5 * (h.comp[A].lj_sig[a] + h.comp[B].lj_sig[b]);
-          LJPair &p = h.lj[A][B][a][b];
-          p.eps4 = 4.0 * eps;
-          p.eps24 = 24.0 * eps;
-          p.sig2 = sig * sig;
-          p.pe = 0.5 / h.comp[A].lj_eps[a];
-          p.ps = 0.5 * h.eta[A][B] * 4.0 * eps / sig;
-          if (h.lj_shift) {
-            const double c2 = sig * sig / h.rc2;
-            const double c6 = c2 * c2 * c2;
-            p.shift = 4.0 * eps * (c6 * c6 - c6);
-            p.csh = 12.0 * c6 * c6 - 6.0 * c6;
-          } else {
-            p.shift = 0.0;
-            p.csh = 0.0;
-          }
-          h.shift_sum[A][B] += p.shift;
-        }
+  mix_lj(h);
   const md_component_desc &d0 = comps[0];
   tmp.single_site = ncomp == 1 && d0.n_lj == 1 && d0.n_chg + d0.n_dip + d0.n_quad == 0 && d0.lj_pos[0] == 0.0 &&
                     d0.lj_pos[1] == 0.0 && d0.lj_pos[2] == 0.0;
@@ -292,6 +320,37 @@ int md_model_destroy(md_model *m) {
 
 int64_t md_param_count(const md_model *m) { return m ? m->nparam : -1; }
 
+int md_model_get_params(const md_model *m, double *params) {
+  if (!m || !params) return set_error(MD_EINVAL, "md_model_get_params: NULL argument");
+  ModelDev h = m->host;
+  int64_t k = 0;
+  for_each_param(h, [&](double &v, bool) { params[k++] = v; });
+  return MD_OK;
+}
+
+int md_model_set_params(md_model *m, const double *params) {
+  if (!m || !params) return set_error(MD_EINVAL, "md_model_set_params: NULL argument");
+  for (int64_t k = 0; k < m->nparam; ++k)
+    if (!std::isfinite(params[k])) return set_error(MD_ENONFINITE, "md_model_set_params: non-finite parameter");
+  ModelDev h = m->host;
+  int64_t k = 0;
+  bool ok = true;
+  for_each_param(h, [&](double &v, bool positive) {
+    v = params[k++];
+    if (positive && !(v > 0.0)) ok = false;
+  });
+  if (!ok) return set_error(MD_EINVAL, "md_model_set_params: LJ epsilon and sigma must be > 0");
+  if (m->single_site && (h.comp[0].lj_pos[0][0] != 0.0 || h.comp[0].lj_pos[0][1] != 0.0 || h.comp[0].lj_pos[0][2] != 0.0))
+    return set_error(MD_EINVAL, "md_model_set_params: the site of a single-site model stays at the centre of mass");
+  mix_lj(h);
+  // kernels still reading the old tables finish first
+  int rc = check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  if (rc) return rc;
+  if ((rc = check_hip(hipMemcpy(m->dev, &h, sizeof(ModelDev), hipMemcpyHostToDevice), "hipMemcpy(model)"))) return rc;
+  m->host = h;
+  return MD_OK;
+}
+
 int md_cells_create(md_cells **out) {
   if (!out) return set_error(MD_EINVAL, "md_cells_create: out is NULL");
   *out = new md_cells();
@@ -302,7 +361,7 @@ int md_cells_destroy(md_cells *c) {
   if (!c) return MD_OK;
   dfree(c->cell_of), dfree(c->slot), dfree(c->tmp), dfree(c->perm), dfree(c->perm_prev), dfree(c->scomp);
   dfree(c->count), dfree(c->start), dfree(c->bsum), dfree(c->lstart);
-  dfree(c->sx), dfree(c->sy), dfree(c->sz), dfree(c->svec);
+  dfree(c->sx), dfree(c->sy), dfree(c->sz), dfree(c->svec), dfree(c->squat);
   delete c;
   return MD_OK;
 }
@@ -360,6 +419,7 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
     if ((rc = grow(c->svec, cap, std::max<int64_t>(1, (int64_t)nvec * 3 * c->cap_N), "svec"))) return rc;
     c->cap_nvec = nvec;
   }
+  if (!m->single_site && (rc = grow(c->squat, c->cap_squat, 4 * N, "squat"))) return rc;
   if (ncell + 1 > capC) {
     int64_t cap = 0;
     c->counts_zero = false;
@@ -381,7 +441,6 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
   for (int k = 0; k < 3; ++k) c->nc[k] = nc[k], c->box[k] = box[k];
   c->nvec = nvec;
   c->model = m;
-  c->quat = quat;
   c->built = false;
   const double inv_h[3] = {(double)nc[0] / box[0], (double)nc[1] / box[1], (double)nc[2] / box[2]};
   hipEvent_t ev;
@@ -464,8 +523,15 @@ int md_step(md_model *m, md_cells *c, double *pos, double *vel, double *quat, do
   // overlaps the next step; the pair and kinetic partial rows then alternate between two slots
   const bool overlap = energies && !nvt && nsteps > 1;
   int64_t slot_sz = 0;
+  // an error return after a side-stream reduction has been queued first orders the caller's
+  // stream after the last one, so that no queued reduction writes `energies` after the return
+  int last_red = -1;
+  auto fail = [&](int code) {
+    if (last_red >= 0) (void)hipStreamWaitEvent(s, m->ev_red[last_red], 0);
+    return code;
+  };
   for (int64_t st = 0; st < nsteps; ++st) {
-    if ((rc = md_build_cells(m, c, pos, quat, comp, N, box, stream))) return rc;
+    if ((rc = md_build_cells(m, c, pos, quat, comp, N, box, stream))) return fail(rc);
     if (overlap && st == 0) {  // the grid is fixed within the call (same box, same cutoff)
       slot_sz = pair_blocks(c->ncell) * PARTIAL_COLS + KIN_COLS * ((3 * N + 255) / 256 + (N + 255) / 256);
       if ((rc = grow(m->partial, m->cap_partial, 2 * slot_sz, "partial"))) return rc;
@@ -482,12 +548,12 @@ int md_step(md_model *m, md_cells *c, double *pos, double *vel, double *quat, do
     double *part = overlap ? m->partial + slot * slot_sz : nullptr;
     // the reduction of step st - 2 has read this slot
     if (overlap && st >= 2 && (rc = check_hip(hipStreamWaitEvent(s, m->ev_red[slot], 0), "hipStreamWaitEvent")))
-      return rc;
+      return fail(rc);
     double *erow = energies ? energies + 4 * st : nullptr;
     int64_t nbp = 0;
     if ((rc = forces_impl(m, c, precision, m->force, m->single_site ? nullptr : m->torque, nullptr, nullptr, nullptr,
                           m->uw + 8, nullptr, erow, s, false, &nbp, part)))
-      return rc;
+      return fail(rc);
     if (!part) part = m->partial;
     hipEvent_t ev;
     prof_begin(m, PROF_STEP, s, &ev);
@@ -503,13 +569,18 @@ int md_step(md_model *m, md_cells *c, double *pos, double *vel, double *quat, do
       if (!rc) rc = check_hip(hipStreamWaitEvent(m->side, m->ev_leap[slot], 0), "hipStreamWaitEvent");
       if (!rc) rc = launch_reduce_forces(m, nbp, part, m->uw + 8, nullptr, erow, m->side, kin, nkin);
       if (!rc) rc = check_hip(hipEventRecord(m->ev_red[slot], m->side), "hipEventRecord");
+      if (!rc) last_red = slot;
     } else if (!rc && (erow || nvt)) {
       rc = launch_reduce_forces(m, nbp, part, m->uw + 8, nullptr, erow, s, kin, nkin);
     }
     if (!rc && nvt)
       rc = launch_rescale(m, vel, angmom, m->host.ncomp > 1 ? comp : nullptr, N, m->uw + 13, m->T_target, s);
     prof_end(m, PROF_STEP, s, ev);
-    if (rc) return rc;
+    if (rc) {
+      // a reduction queued on the side stream whose event was not recorded: wait for all of it
+      if (overlap && m->side) (void)hipStreamSynchronize(m->side);
+      return fail(rc);
+    }
   }
   // the caller's stream sees every reduction of this call
   if (overlap && (rc = check_hip(hipStreamWaitEvent(s, m->ev_red[(nsteps - 1) & 1], 0), "hipStreamWaitEvent")))
@@ -602,7 +673,7 @@ int md_forces_adjoint(md_model *m, const md_cells *c, int precision, double gU, 
   int64_t nblocks = 0;
   hipEvent_t ev;
   prof_begin(m, PROF_ADJ, s, &ev);
-  rc = launch_adjoint(m, c, precision, o, m->single_site ? nullptr : c->quat, s, &nblocks);
+  rc = launch_adjoint(m, c, precision, o, m->single_site ? nullptr : c->squat, s, &nblocks);
   if (!rc && pg) rc = launch_reduce(m, nblocks, (int)m->nparam, pg, dparams, s);
   prof_end(m, PROF_ADJ, s, ev);
   if (rc) return rc;

@@ -40,7 +40,8 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
   const int64_t i = valid ? (a.order ? (int64_t)a.order[d] : d) : 0;
   double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
   int flags = 0;
-  if (!(isfinite(x) && isfinite(y) && isfinite(z))) {
+  const bool finite = isfinite(x) && isfinite(y) && isfinite(z);
+  if (!finite) {
     flags |= MD_DEV_NONFINITE;
     x = y = z = 0.0;
   }
@@ -57,7 +58,10 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
   const int cx = bin1(wrap1(x, a.Lx), a.ihx, a.nx);
   const int cy = bin1(wrap1(y, a.Ly), a.ihy, a.ny);
   const int cz = bin1(wrap1(z, a.Lz), a.ihz, a.nz);
-  const int cell = valid ? (cz * a.ny + cy) * a.nx + cx : -1;
+  // a molecule with a non-finite coordinate goes to cell i mod ncell, so that such molecules
+  // (a run that blew up) spread over the grid instead of crowding one cell; its sorted copy is
+  // NaN, which fails every cutoff test, so it has no partners
+  const int cell = !valid ? -1 : (finite ? (cz * a.ny + cy) * a.nx + cx : (int)(i % (int64_t)(a.nx * a.ny * a.nz)));
   // runs of equal cells among consecutive lanes: the run head adds the run length
   const int prev = __shfl_up(cell, 1, 64);
   const bool head = lane == 0 || prev != cell;
@@ -167,7 +171,7 @@ struct GatherArgs {
   const ModelDev *md;
   int32_t sl, sc, sd, sq, nvec;
   int32_t *perm, *scomp;
-  double *sx, *sy, *sz, *svec;
+  double *sx, *sy, *sz, *svec, *squat;
 };
 
 __device__ __forceinline__ void rotate(const double q[4], const double v[3], double o[3]) {
@@ -194,7 +198,7 @@ __global__ __launch_bounds__(256) void k_rank_gather(GatherArgs a) {
   const int d = s + rank;
   a.perm[d] = (int32_t)i;
   double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
-  if (!(isfinite(x) && isfinite(y) && isfinite(z))) x = y = z = 0.0;
+  if (!(isfinite(x) && isfinite(y) && isfinite(z))) x = y = z = __builtin_nan("");
   a.sx[d] = wrap1(x, a.Lx);
   a.sy[d] = wrap1(y, a.Ly);
   a.sz[d] = wrap1(z, a.Lz);
@@ -209,6 +213,7 @@ __global__ __launch_bounds__(256) void k_rank_gather(GatherArgs a) {
     double q[4] = {1.0, 0.0, 0.0, 0.0};
     if (a.quat)
       for (int k = 0; k < 4; ++k) q[k] = a.quat[4 * i + k];
+    for (int k = 0; k < 4; ++k) a.squat[4 * d + k] = q[k];
     double *out = a.svec + (int64_t)d * a.nvec * 3;
     double o[3];
     const double zero[3] = {0.0, 0.0, 0.0};
@@ -301,7 +306,7 @@ int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat
   GatherArgs g{pos, m->single_site ? nullptr : quat, comp, c->cell_of, c->start, c->tmp, order, N,
                c->box[0], c->box[1], c->box[2], m->dev, m->shape.lj, m->shape.chg, m->shape.dip, m->shape.quad,
                c->nvec, c->perm, m->single_site ? nullptr : c->scomp, c->sx, c->sy, c->sz,
-               m->single_site ? nullptr : c->svec};
+               m->single_site ? nullptr : c->svec, m->single_site ? nullptr : c->squat};
   k_rank_gather<<<nblk(N, 256), 256, 0, s>>>(g);
   return check_hip(hipGetLastError(), "k_rank_gather");
 }

@@ -61,6 +61,7 @@ struct CellsDev {
   const int32_t *cell_start, *perm, *scomp;
   const double *sx, *sy, *sz;  // wrapped COMs in sorted order
   const double *svec;          // [N][nvec][3] world-frame site offsets / axes, sorted order
+  const double *squat;         // [N][4] quaternions in sorted order (multi-site models), or NULL
   int32_t nx, ny, nz, ncell, nvec;
   double Lx, Ly, Lz, hx, hy, hz;
 };
@@ -105,13 +106,16 @@ struct md_cells {
   int nvec = 0, cap_nvec = 0;
   bool built = false;
   const md_model *model = nullptr;
-  const double *quat = nullptr;  // caller's quaternion array of the last build (read by the adjoint)
   int32_t *cell_of = nullptr, *slot = nullptr, *tmp = nullptr, *perm = nullptr, *scomp = nullptr;
   int32_t *perm_prev = nullptr;  // the other buffer of the permutation pair (previous build's order)
   int32_t *count = nullptr, *start = nullptr, *bsum = nullptr;
   int32_t *lstart = nullptr;     // tile-local exclusive prefix of the counts
   bool counts_zero = false;      // every entry of the count allocation is zero (left so by the scan)
   double *sx = nullptr, *sy = nullptr, *sz = nullptr, *svec = nullptr;
+  // quaternions of the last build in sorted order (multi-site models): the adjoint's dU/dq
+  // chain rule reads these, so it never depends on the caller's array after the build
+  double *squat = nullptr;
+  int64_t cap_squat = 0;
 };
 
 struct md_model {

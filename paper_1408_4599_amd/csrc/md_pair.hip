@@ -1182,6 +1182,7 @@ CellsDev cells_dev(const md_cells *c) {
   d.scomp = c->scomp;
   d.sx = c->sx, d.sy = c->sy, d.sz = c->sz;
   d.svec = c->svec;
+  d.squat = c->squat;
   d.nx = c->nc[0], d.ny = c->nc[1], d.nz = c->nc[2];
   d.ncell = (int32_t)c->ncell;
   d.nvec = c->nvec;

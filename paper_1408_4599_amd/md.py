@@ -80,11 +80,15 @@ def lib():
     L.md_profile.argtypes = [vp, ctypes.c_int]
     L.md_profile_read.argtypes = [vp, ctypes.c_char_p, _dp, _lp]
     L.md_set_thermostat.argtypes = [vp, ctypes.c_double]
+    L.md_model_get_params.argtypes = [vp, _dp]
+    L.md_model_set_params.argtypes = [vp, _dp]
     L.md_long_range_correction.argtypes = [ctypes.POINTER(ComponentDesc), ctypes.c_int32, _dp, _dp, ctypes.c_double,
                                            ctypes.c_uint32, _lp, _dp, _dp, _dp]
     for name in ("md_model_create", "md_model_destroy", "md_cells_create", "md_cells_destroy", "md_cells_view",
-                 "md_build_cells", "md_forces", "md_step", "md_forces_adjoint", "md_status", "md_profile",
-                 "md_profile_read", "md_set_thermostat", "md_long_range_correction"):
+                 "md_build_cells", "md_forces", "md_step", "md_forces_adjoint", "md_status",
+                 "md_profile",
+                 "md_profile_read", "md_set_thermostat", "md_long_range_correction", "md_model_get_params",
+                 "md_model_set_params"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -225,6 +229,21 @@ class Model:
         _check(lib().md_profile_read(self.handle, group.encode(), ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
 
+    def params(self) -> np.ndarray:
+        """The differentiable parameters (md_model_get_params), host FP64 [nparam] in the layout
+        of md_forces_adjoint's dparams."""
+        out = np.zeros(max(1, self.nparam), dtype=np.float64)
+        _check(lib().md_model_get_params(self.handle, out.ctypes.data_as(_dp)))
+        return out[:self.nparam]
+
+    def set_params(self, params):
+        """Replace the differentiable parameters (md_model_set_params; syncs the device)."""
+        a = np.ascontiguousarray(np.asarray(params.detach().cpu() if isinstance(params, torch.Tensor) else params,
+                                            dtype=np.float64).reshape(-1))
+        if a.shape[0] != self.nparam:
+            raise ValueError(f"params: expected {self.nparam} values, got {a.shape[0]}")
+        _check(lib().md_model_set_params(self.handle, a.ctypes.data_as(_dp)))
+
     def param_layout(self):
         """List of (component, kind, index, names) in the order of md_forces_adjoint's dparams."""
         out = []
@@ -362,33 +381,49 @@ def forces_adjoint(model: Model, cells: Cells, precision="fp64", gU=1.0, want_qu
 
 
 class EnergyFn(torch.autograd.Function):
-    """U(pos, quat) as a differentiable FP64 scalar.  Forward runs md_build_cells + md_forces;
-    backward re-traverses the cells with md_forces_adjoint (recomputation, no stored pair list).
-    Parameter gradients are available through ``forces_adjoint`` (the model tables live in the
-    library, not in torch tensors)."""
+    """U(pos, quat, params) as a differentiable FP64 scalar.  Forward sets the model's parameters
+    from ``params`` (when given: a FP64 tensor in the layout of ``Model.params()``), then runs
+    md_build_cells + md_forces; backward re-traverses the cells with md_forces_adjoint
+    (recomputation, no stored pair list) and returns gradients for pos, quat and params.  The
+    contiguous copies handed to the library live until the adjoint has run."""
 
     @staticmethod
-    def forward(ctx, pos, quat, model, cells, box, comp, precision):
-        build_cells(model, cells, pos.detach().contiguous(), None if quat is None else quat.detach().contiguous(),
-                    comp, box)
+    def forward(ctx, pos, quat, params, model, cells, box, comp, precision):
+        if params is not None:
+            model.set_params(params)
+        pos_c = pos.detach().contiguous()
+        quat_c = None if quat is None else quat.detach().contiguous()
+        build_cells(model, cells, pos_c, quat_c, comp, box)
         r = forces(model, cells, precision, torque=False, per_molecule=False)
         ctx.model, ctx.cells, ctx.precision = model, cells, precision
         ctx.has_quat = quat is not None
-        ctx.save_for_backward(pos, quat if quat is not None else torch.empty(0, device=pos.device), comp if comp is not None else torch.empty(0, device=pos.device))
+        ctx.has_params = params is not None
+        empty = torch.empty(0, device=pos.device)
+        ctx.save_for_backward(pos, quat if quat is not None else empty, comp if comp is not None else empty,
+                              params.detach() if params is not None else empty)
         ctx.box = box
         return r["uw"][0].clone()
 
     @staticmethod
     def backward(ctx, gU):
-        pos, quat, comp = ctx.saved_tensors
-        quat_t = quat if ctx.has_quat else None
+        pos, quat, comp, params = ctx.saved_tensors
         comp_t = comp if comp.numel() else None
-        build_cells(ctx.model, ctx.cells, pos.detach().contiguous(),
-                    None if quat_t is None else quat_t.detach().contiguous(), comp_t, ctx.box)
+        if ctx.has_params:  # another forward may have changed the model since
+            ctx.model.set_params(params)
+        pos_c = pos.detach().contiguous()
+        quat_c = quat.detach().contiguous() if ctx.has_quat else None
+        build_cells(ctx.model, ctx.cells, pos_c, quat_c, comp_t, ctx.box)
+        want_params = ctx.has_params and ctx.needs_input_grad[2]
         g = forces_adjoint(ctx.model, ctx.cells, ctx.precision, float(gU.item()), want_quat=ctx.has_quat,
-                           want_params=False)
-        return g["dpos"], (g["dquat"] if ctx.has_quat else None), None, None, None, None, None
+                           want_params=want_params)
+        dparams = None
+        if want_params:
+            dparams = (g["dparams"][:ctx.model.nparam].to(params.device) if ctx.model.nparam > 0
+                       else torch.zeros_like(params))
+        return g["dpos"], (g["dquat"] if ctx.has_quat else None), dparams, None, None, None, None, None
 
 
-def energy(pos, quat, model, cells, box, comp=None, precision="fp64"):
-    return EnergyFn.apply(pos, quat, model, cells, box, comp, precision)
+def energy(pos, quat, model, cells, box, comp=None, precision="fp64", params=None):
+    """U through EnergyFn; ``params`` (optional FP64 tensor, layout of ``Model.params()``) makes
+    the model's parameters differentiable inputs."""
+    return EnergyFn.apply(pos, quat, params, model, cells, box, comp, precision)

@@ -30,3 +30,23 @@ def run_forces(md, cfg, precision="fp64", pos=None, quat=None, comp=None, model=
 
 def rel_rms(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def elem_err(a, b):
+    """Largest per-molecule error, max_i |a_i - b_i| (Euclidean norm over molecule i's row), over
+    the RMS per-molecule magnitude of b.  A bound on every molecule, so that an error confined to
+    a few molecules (one tile path, one fix-up row) cannot hide inside a global RMS."""
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    if a.ndim == 1:
+        a, b = a[:, None], b[:, None]
+    scale = np.sqrt(np.mean(np.sum(b * b, axis=1)))
+    return float(np.linalg.norm(a - b, axis=1).max() / max(scale, 1e-300))
+
+
+def assert_close(a, b, rms_bar, what="", elem_bar=None):
+    """Global relative RMS below rms_bar and every molecule's error below elem_bar (default
+    10 rms_bar) times the RMS magnitude; returns both errors."""
+    elem_bar = 10.0 * rms_bar if elem_bar is None else elem_bar
+    e, m = rel_rms(a, b), elem_err(a, b)
+    assert e < rms_bar and m < elem_bar, f"{what}: rel RMS {e:.2e} (bar {rms_bar:.0e}), max per molecule {m:.2e} (bar {elem_bar:.0e})"
+    return e, m

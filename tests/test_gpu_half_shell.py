@@ -9,7 +9,7 @@ the conservation laws of an isolated cluster."""
 import numpy as np
 import pytest
 
-from tests._gpu import dev, rel_rms, run_forces
+from tests._gpu import assert_close, dev, elem_err, rel_rms, run_forces
 from tests.test_gpu_parity import _ms_cluster
 from paper_1408_4599_amd import workloads as W
 
@@ -48,11 +48,14 @@ def _check(md, oracle, cfg, prec, bar, ubar=1e-9):
     np.testing.assert_array_equal(got["nnb"], ref["nnb"])
     assert got["npairs"] == ref["nnb"].sum() // 2
     eF, eT = rel_rms(got["force"], ref["F"]), rel_rms(got["torque"], ref["T"])
+    mF, mT = elem_err(got["force"], ref["F"]), elem_err(got["torque"], ref["T"])
     eu = rel_rms(got["u_mol"], ref["u"])
     eU = abs(got["U"] - ref["u"].sum()) / abs(ref["u"].sum())
-    print(f"  {prec}: eps_F {eF:.2e} eps_T {eT:.2e} eps_u {eu:.2e} eps_U {eU:.2e}", flush=True)
+    print(f"  {prec}: eps_F {eF:.2e} (max {mF:.2e}) eps_T {eT:.2e} (max {mT:.2e}) eps_u {eu:.2e} eps_U {eU:.2e}",
+          flush=True)
     assert eF < bar and eT < bar
-    assert eu < (1e-11 if prec == "fp64" else 1e-6)
+    assert mF < 10 * bar and mT < 10 * bar
+    assert_close(got["u_mol"], ref["u"], 1e-11 if prec == "fp64" else 1e-6, "u_mol")
     assert eU < (1e-12 if prec == "fp64" else ubar)
     assert m.status() == 0
     return got
@@ -83,8 +86,10 @@ def test_overlapping_molecules_take_the_fp64_fixup(md, oracle, args):
         assert np.all(np.isfinite(a["force"])) and np.all(np.isfinite(a["torque"]))
         np.testing.assert_array_equal(a["nnb"], ref["nnb"])
         eF, eT = rel_rms(a["force"], ref["F"]), rel_rms(a["torque"], ref["T"])
-        print(f"  {prec}: eps_F {eF:.2e} eps_T {eT:.2e}", flush=True)
+        mF, mT = elem_err(a["force"], ref["F"]), elem_err(a["torque"], ref["T"])
+        print(f"  {prec}: eps_F {eF:.2e} (max {mF:.2e}) eps_T {eT:.2e} (max {mT:.2e})", flush=True)
         assert eF < bar and eT < bar
+        assert mF < 10 * bar and mT < 10 * bar
         assert m.status() == 0
 
 
@@ -142,13 +147,14 @@ def test_single_site_half_shell_matches_oracle(md, oracle, name):
         np.testing.assert_array_equal(got["nnb"], ref["nnb"])
         assert got["npairs"] == ref["nnb"].sum() // 2
         eF, eU = rel_rms(got["force"], ref["F"]), abs(got["U"] - U) / abs(U)
-        print(f"{name} {prec}: eps_F {eF:.2e} eps_U {eU:.2e}", flush=True)
-        assert eF < fbar and eU < ubar
+        mF = elem_err(got["force"], ref["F"])
+        print(f"{name} {prec}: eps_F {eF:.2e} (max {mF:.2e}) eps_U {eU:.2e}", flush=True)
+        assert eF < fbar and eU < ubar and mF < 10 * fbar
         assert np.all(got["torque"] == 0.0)
         if prec == "fp64":
             assert got["W"] == pytest.approx(ref["w"].sum(), rel=1e-12)
-            assert rel_rms(got["u_mol"], ref["u"]) < 1e-11
-            assert rel_rms(got["w_mol"], ref["w"]) < 1e-11
+            assert_close(got["u_mol"], ref["u"], 1e-11, "u_mol")
+            assert_close(got["w_mol"], ref["w"], 1e-11, "w_mol")
         assert m.status() == 0
 
 

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from tests._gpu import dev
+from tests._gpu import assert_close, dev
 from paper_1408_4599_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -79,6 +79,37 @@ def test_step_nvt_matches_oracle_trajectory(md, oracle, name, nsteps, tol):
     f = 3 * N + (0 if cfg["quat"] is None else sum(int(np.sum(np.asarray(comps[c]["inertia"]) > 0)) for c in comp))
     T = 2.0 * (e[:, 1] + e[:, 2]) / f
     assert abs(T[-1] - T_target) < abs(T[0] - T_target)
+
+
+@pytest.mark.parametrize("name", ["c1_ljts_4000", "c4_small"])
+def test_step_fp32_matches_oracle_trajectory(md, oracle, name):
+    """The FP32 md_step (the path behind the benchmark's step rate) against the FP64 oracle's
+    integrator over 10 steps.  The FP32 force error (below 1e-5 relative) moves a molecule by
+    about (10 dt)^2 |dF| / 2 m, some 1e-8 here, so positions are held to 1e-7 absolute, velocities
+    and angular momenta to 1e-5 and quaternions to 1e-6.  Per step: U at the FP32 energy bar
+    (1e-9 relative), K_trans and K_rot at 1e-8 (velocity errors of 1e-7 relative average out
+    over the molecules), W at 1e-6 (it carries the FP32 force scalars)."""
+    cfg = W.make(name)
+    nsteps = 10
+    p_ref, v_ref, q_ref, j_ref, e_ref = oracle.step(cfg["model"], cfg["pos"], cfg["vel"], cfg["quat"], cfg["angmom"],
+                                                    cfg["comp"], cfg["box"], cfg["dt"], nsteps)
+    p, v, q, j, e = _run_gpu(md, cfg, nsteps, "fp32")
+    dp = np.abs(_min_image(p - p_ref, cfg["box"])).max()
+    dv = np.abs(v - v_ref).max()
+    print(f"{name}: max |dpos| {dp:.2e} max |dvel| {dv:.2e}", flush=True)
+    assert dp < 1e-7 and dv < 1e-5
+    if q is not None:
+        dq, dj = np.abs(q - q_ref).max(), np.abs(j - j_ref).max()
+        print(f"  max |dquat| {dq:.2e} max |dangmom| {dj:.2e}", flush=True)
+        assert dq < 1e-6 and dj < 1e-5
+    rel = np.abs(e - e_ref) / np.abs(e_ref).max(axis=0).clip(1e-300)
+    print(f"  per-step relative errors U {rel[:, 0].max():.2e} K_trans {rel[:, 1].max():.2e} "
+          f"K_rot {rel[:, 2].max():.2e} W {rel[:, 3].max():.2e}", flush=True)
+    assert rel[:, 0].max() < 1e-9
+    assert rel[:, 1].max() < 1e-8
+    if q is not None:
+        assert rel[:, 2].max() < 1e-8
+    assert rel[:, 3].max() < 1e-6
 
 
 def test_step_nve_fp32_energy_conservation(md):
