@@ -188,6 +188,26 @@ int md_build_cells(md_model *m, md_cells *cells, const double *pos, const double
 int md_forces(md_model *m, const md_cells *cells, int precision, double *force, double *torque, double *u_mol,
               double *w_mol, int32_t *nnb_mol, double *uw, int64_t *npairs, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): md_forces with its per-call scratch -- the pair
+ * kernel's block partials and, for multi-site models and MD_HALF_SHELL, the per-molecule partner
+ * rows -- in one static device array of MD_NOALLOC_SCRATCH_BYTES per GPU, held until the process
+ * ends, instead of model-owned buffers.  Arguments, kernels and results are those of md_forces,
+ * bit for bit.  It calls no hipMalloc / hipFree; the model's fixed tables (md_model_create) and
+ * the cells (md_build_cells, which allocates only when they grow) are used as they are.  The
+ * scratch needed is 40 bytes per cell and 1 byte per molecule (block partials) plus, for the
+ * half-shell kernels, 15 partner rows per molecule: 180 B (single-site) or 360 B (multi-site) in
+ * FP32, twice that in FP64, and 360 B more when u_mol, w_mol or nnb_mol is given.  A
+ * configuration that needs more than the array returns MD_EINVAL with nothing enqueued: beyond
+ * about 400 000 cells for single-site models without MD_HALF_SHELL, beyond about 23 000
+ * molecules for multi-site FP32 with per-molecule outputs.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on one GPU (two streams,
+ * two threads) race and give wrong results.  The array needs no clearing: every call overwrites
+ * what it reads.  Errors as md_forces. */
+#define MD_NOALLOC_SCRATCH_BYTES (16u << 20)
+int md_forces_noalloc(md_model *m, const md_cells *cells, int precision, double *force, double *torque,
+                      double *u_mol, double *w_mol, int32_t *nnb_mol, double *uw, int64_t *npairs, void *stream);
+
 /* nsteps leapfrog steps (Sec. 3, Eqs. 2-5), each: build cells, forces/torques at t,
  *   v(t + dt/2) = v(t - dt/2) + dt F / m,  r(t + dt) = r(t) + dt v(t + dt/2)  (wrapped),
  * and for molecules with inertia, Fincham's rotational leapfrog with the space-frame angular

@@ -457,33 +457,52 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
   return sync_check(m, s);
 }
 
+// Scratch of one pair evaluation, in doubles: the block partials, and for the half-shell kernels
+// (multi-site models, MD_HALF_SHELL) the per-molecule partner rows of force (and torque) in the
+// path's precision followed, 256-byte aligned, by the FP64 u, w and count rows when per-molecule
+// outputs are wanted (nq = 9).
+struct PairScratch {
+  int64_t partial, ft, uw;  // doubles of each part; rows = ft + uw
+};
+static PairScratch pair_scratch(const md_model *m, const md_cells *c, int precision, int nq) {
+  PairScratch r{};
+  r.partial = pair_blocks(c->ncell) * PARTIAL_COLS + KIN_COLS * ((3 * c->N + 255) / 256 + (c->N + 255) / 256);
+  const bool half_shell = !m->single_site || (m->flags & MD_HALF_SHELL);
+  if (half_shell) {
+    const int64_t ft_bytes = (int64_t)N3_ROWS * c->N * (m->single_site ? 3 : 6) * (precision == MD_FP32 ? 4 : 8);
+    r.ft = (ft_bytes + 255) / 256 * 32;
+    r.uw = nq > 6 ? (int64_t)N3_ROWS * c->N * 3 : 0;
+  }
+  return r;
+}
+
 // Pair kernel (+ the reduction of its block partials unless reduce is false: md_step reduces them
-// together with the leapfrog's kinetic-energy partials, which follow them in m->partial).
+// together with the leapfrog's kinetic-energy partials, which follow them in m->partial).  With
+// scratch given (md_forces_noalloc) the partials and rows live there and nothing is allocated.
 static int forces_impl(md_model *m, const md_cells *c, int precision, double *force, double *torque, double *u_mol,
                        double *w_mol, int32_t *nnb_mol, double *uw, int64_t *npairs, double *erow, hipStream_t s,
-                       bool reduce = true, int64_t *nblocks_out = nullptr, double *partial = nullptr) {
-  const int64_t nb = pair_blocks(c->ncell);
-  int rc;
-  if ((rc = grow(m->partial, m->cap_partial,
-                 nb * PARTIAL_COLS + KIN_COLS * ((3 * c->N + 255) / 256 + (c->N + 255) / 256), "partial")))
-    return rc;
+                       bool reduce = true, int64_t *nblocks_out = nullptr, double *partial = nullptr,
+                       double *scratch = nullptr) {
   const int nq = (u_mol || w_mol || nnb_mol) ? 9 : 6;
-  // half-shell rows: force (and torque) in the path's precision, then (256-byte aligned) the FP64
-  // u, w, count rows when nq = 9
-  const bool half_shell = !m->single_site || (m->flags & MD_HALF_SHELL);
-  const int64_t ft_bytes = (int64_t)N3_ROWS * c->N * (m->single_site ? 3 : 6) * (precision == MD_FP32 ? 4 : 8);
-  const int64_t ft_doubles = (ft_bytes + 255) / 256 * 32;
-  if (half_shell &&
-      (rc = grow(m->rows, m->cap_rows, ft_doubles + (nq > 6 ? (int64_t)N3_ROWS * c->N * 3 : 0), "pair rows")))
-    return rc;
-  if (!partial) partial = m->partial;
-  PairOut o{force, torque, u_mol, w_mol, nnb_mol, partial, m->rows, m->rows + ft_doubles, c->N, nq, m->status,
+  const PairScratch need = pair_scratch(m, c, precision, nq);
+  int rc;
+  double *rows = nullptr;
+  if (scratch) {
+    partial = scratch;
+    rows = scratch + (need.partial + 31) / 32 * 32;
+  } else {
+    if ((rc = grow(m->partial, m->cap_partial, need.partial, "partial"))) return rc;
+    if (need.ft && (rc = grow(m->rows, m->cap_rows, need.ft + need.uw, "pair rows"))) return rc;
+    rows = m->rows;
+    if (!partial) partial = m->partial;
+  }
+  PairOut o{force, torque, u_mol, w_mol, nnb_mol, partial, rows, rows ? rows + need.ft : nullptr, c->N, nq, m->status,
             m->bad};
   int64_t nblocks = 0;
   hipEvent_t ev;
-  prof_begin(m, PROF_PAIR, s, &ev);
+  if (!scratch) prof_begin(m, PROF_PAIR, s, &ev);
   rc = launch_pair(m, c, precision, o, s, &nblocks);
-  prof_end(m, PROF_PAIR, s, ev);
+  if (!scratch) prof_end(m, PROF_PAIR, s, ev);
   if (rc) return rc;
   if (nblocks_out) *nblocks_out = nblocks;
   return reduce ? launch_reduce_forces(m, nblocks, partial, uw, npairs, erow, s) : MD_OK;
@@ -497,6 +516,29 @@ int md_forces(md_model *m, const md_cells *c, int precision, double *force, doub
   hipStream_t s = (hipStream_t)stream;
   m->last_stream = s;
   int rc = forces_impl(m, c, precision, force, torque, u_mol, w_mol, nnb_mol, uw, npairs, nullptr, s);
+  if (rc) return rc;
+  return sync_check(m, s);
+}
+
+int md_forces_noalloc(md_model *m, const md_cells *c, int precision, double *force, double *torque, double *u_mol,
+                      double *w_mol, int32_t *nnb_mol, double *uw, int64_t *npairs, void *stream) {
+  if (!m || !c || !force || !uw) return set_error(MD_EINVAL, "md_forces_noalloc: NULL argument");
+  if (precision != MD_FP64 && precision != MD_FP32) return set_error(MD_EINVAL, "md_forces_noalloc: bad precision");
+  if (!c->built || c->model != m) return set_error(MD_EINVAL, "md_forces_noalloc: cells not built with this model");
+  const int nq = (u_mol || w_mol || nnb_mol) ? 9 : 6;
+  const PairScratch need = pair_scratch(m, c, precision, nq);
+  const int64_t bytes = 8 * ((need.partial + 31) / 32 * 32 + need.ft + need.uw);
+  if (bytes > (int64_t)MD_NOALLOC_SCRATCH_BYTES)
+    return set_error(MD_EINVAL, "md_forces_noalloc: this configuration needs " + std::to_string(bytes) +
+                                    " bytes of scratch, the static array holds " +
+                                    std::to_string((int64_t)MD_NOALLOC_SCRATCH_BYTES));
+  void *scratch = nullptr;
+  int rc = noalloc_scratch(&scratch);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  m->last_stream = s;
+  rc = forces_impl(m, c, precision, force, torque, u_mol, w_mol, nnb_mol, uw, npairs, nullptr, s, true, nullptr,
+                   nullptr, (double *)scratch);
   if (rc) return rc;
   return sync_check(m, s);
 }

@@ -190,6 +190,9 @@ int launch_leapfrog(md_model *m, double *pos, double *vel, double *quat, double 
                     double *kin_rows, int64_t *kin_nrows, hipStream_t s);
 int launch_adjoint(md_model *m, const md_cells *c, int precision, const AdjOut &o, const double *quat,
                    hipStream_t s, int64_t *nblocks);
+// device address of the static scratch array of md_forces_noalloc on the current device (looked
+// up once per device with hipGetSymbolAddress; md_pair.hip)
+int noalloc_scratch(void **ptr);
 int launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 int launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 int launch_scale_copy(const double *src, double *dst, int64_t n, double a, hipStream_t s);

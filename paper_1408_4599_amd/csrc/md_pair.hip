@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "md_device.h"
@@ -1174,6 +1175,29 @@ int launch_ms(const CellsDev &cd, const md_model *m, const PairOut &o, int64_t n
 }
 
 }  // namespace
+
+// Scratch of md_forces_noalloc: one array per GPU, for the life of the process.  In host code
+// `scratch` names a host-side stand-in, never the device memory: kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) static unsigned char scratch[MD_NOALLOC_SCRATCH_BYTES];
+
+int noalloc_scratch(void **ptr) {
+  constexpr int MAXDEV = 64;
+  static std::mutex mu;
+  static void *addr[MAXDEV] = {};
+  int dev = 0;
+  int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if (dev < 0 || dev >= MAXDEV) return set_error(MD_EINVAL, "md_forces_noalloc: device ordinal beyond 63");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    if ((rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"))) return rc;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return MD_OK;
+}
 
 CellsDev cells_dev(const md_cells *c) {
   CellsDev d;

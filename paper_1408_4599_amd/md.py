@@ -73,6 +73,7 @@ def lib():
     L.md_cells_view.argtypes = [vp, ctypes.POINTER(CellsInfo)]
     L.md_build_cells.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, _dp, vp]
     L.md_forces.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.md_forces_noalloc.argtypes = [vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
     L.md_step.argtypes = [vp, vp, vp, vp, vp, vp, vp, ctypes.c_int64, _dp, ctypes.c_double, ctypes.c_int64,
                           ctypes.c_int, vp, vp]
     L.md_forces_adjoint.argtypes = [vp, vp, ctypes.c_int, ctypes.c_double, vp, vp, vp, vp]
@@ -85,7 +86,7 @@ def lib():
     L.md_long_range_correction.argtypes = [ctypes.POINTER(ComponentDesc), ctypes.c_int32, _dp, _dp, ctypes.c_double,
                                            ctypes.c_uint32, _lp, _dp, _dp, _dp]
     for name in ("md_model_create", "md_model_destroy", "md_cells_create", "md_cells_destroy", "md_cells_view",
-                 "md_build_cells", "md_forces", "md_step", "md_forces_adjoint", "md_status",
+                 "md_build_cells", "md_forces", "md_forces_noalloc", "md_step", "md_forces_adjoint", "md_status",
                  "md_profile",
                  "md_profile_read", "md_set_thermostat", "md_long_range_correction", "md_model_get_params",
                  "md_model_set_params"):
@@ -344,6 +345,14 @@ def forces_into(model: Model, cells: Cells, precision, out: dict):
     _check(lib().md_forces(model.handle, cells.handle, PRECISION[precision], _ptr(out["force"]),
                            _ptr(out.get("torque")), _ptr(out.get("u_mol")), _ptr(out.get("w_mol")),
                            _ptr(out.get("nnb")), _ptr(out["uw"]), _ptr(out.get("npairs")), _stream()))
+
+
+def forces_into_noalloc(model: Model, cells: Cells, precision, out: dict):
+    """md_forces_noalloc into preallocated tensors (keys as ``forces``): the same results with the
+    per-call scratch in the library's static device array (no device allocation)."""
+    _check(lib().md_forces_noalloc(model.handle, cells.handle, PRECISION[precision], _ptr(out["force"]),
+                                   _ptr(out.get("torque")), _ptr(out.get("u_mol")), _ptr(out.get("w_mol")),
+                                   _ptr(out.get("nnb")), _ptr(out["uw"]), _ptr(out.get("npairs")), _stream()))
 
 
 def step(model: Model, cells: Cells, pos, vel, quat, angmom, comp, box, dt, nsteps, precision="fp64",
