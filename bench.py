@@ -81,7 +81,7 @@ def pair_counters(kernel_sources):
     counter summary, if it was taken on the current kernel source (hash recorded in the summary);
     else (None, None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_pair_lj1_c2_lj_1m_counters.md")
+    path = os.path.join(ROOT, "profiles", "k_pair_lj_c2_lj_1m_counters.md")
     if not os.path.exists(path):
         return None, None
     h = hashlib.sha256()
@@ -357,7 +357,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": W_alg / f32_pair / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": W_alg / f32_pair / PEAK_FP32,
                      "traffic": traffic,
-                     "kernel": "k_pair_lj1<float>" if model.single_site else "k_pair_ms<float>",
+                     "kernel": "k_pair_lj<float>" if model.single_site else "k_pair_ms<float>",
                      "algorithmic_flop_per_launch": W_alg,
                      "accounting": f"{DIST_TEST_FLOP} FLOP per half-shell distance test (D) + "
                                    f"{pair_flops(cfg['model'])} FLOP per unique interacting pair (P)",

@@ -150,7 +150,9 @@ __device__ void lj1_cell_chunked(const CellsDev &c, const LJPair &p, double rc2,
 
 // Fixed-order block reduction of the five partial columns (wave shuffles, then waves in order).
 template <int NW>
-__device__ __forceinline__ void write_partial_block(double *partial, double acc5[5], double (*red)[5]) {
+__device__ __forceinline__ void write_partial_block(double *partial, double acc5[5], double (*red)[5],
+                                                    int64_t row = -1) {
+  if (row < 0) row = blockIdx.x;
 #pragma unroll
   for (int q = 0; q < 5; ++q)
 #pragma unroll
@@ -158,7 +160,7 @@ __device__ __forceinline__ void write_partial_block(double *partial, double acc5
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (NW == 1) {
     if (lane == 0) {
-      double *pp = partial + (int64_t)blockIdx.x * PARTIAL_COLS;
+      double *pp = partial + row * PARTIAL_COLS;
       for (int q = 0; q < 5; ++q) pp[q] = acc5[q];
     }
     return;
@@ -167,7 +169,7 @@ __device__ __forceinline__ void write_partial_block(double *partial, double acc5
     for (int q = 0; q < 5; ++q) red[wave][q] = acc5[q];
   __syncthreads();
   if (threadIdx.x == 0) {
-    double *pp = partial + (int64_t)blockIdx.x * PARTIAL_COLS;
+    double *pp = partial + row * PARTIAL_COLS;
     for (int q = 0; q < 5; ++q) {
       double v = red[0][q];
       for (int w = 1; w < NW; ++w) v += red[w][q];
@@ -182,32 +184,98 @@ __device__ __forceinline__ void write_partial_block(double *partial, double acc5
 // stencil is three contiguous segments of nine cells (3 in x by 3 in y, one segment per z-layer).
 // In a wavefront with n home molecules, lane l < n NS (NS = min(8, floor(64 / n))) takes molecule
 // l % n and, in each segment, candidates s, s + NS, ... with s = l / n: all molecule lanes of a
-// slice read the same partner, so LDS reads broadcast.  Pass 1 runs only the exact FP64 cutoff
-// test and appends hits to a per-lane list in LDS; when a list could overflow, the listed hits are
-// evaluated (pass 2) and the lists restart, so the pair arithmetic runs for partners inside the
-// cutoff only.  A block whose tile exceeds the LDS capacity walks the same candidates in the same
-// order through per-wavefront windows of its segments: the same pairs, each evaluated the same
-// way.  Only the points where lists are flushed can differ (a window change flushes), which
-// regroups each molecule's sum over its lanes: a difference of rounding.  Slice sums are combined
-// through LDS in a fixed order.  Home cells with more than 64 molecules use
-// lj1_cell_chunked (a decision fixed by the configuration, not by the capacity).
+// slice read the same partner, so LDS reads broadcast.
+//
+// Pass 1 (cutoff test) appends the staged slot of every hit to a per-lane list in LDS.
+//   * FP64 path: the exact test fma(dz, dz, fma(dy, dy, dx * dx)) < r_c^2 on FP64 separations.
+//   * FP32 path: each staged entry also holds x~ = fl32(x - o) relative to the tile centre o and
+//     n~ = fl32(|x~|^2); the test is T = fma(-2 z~_i, z~_j, fma(-2 y~_i, y~_j, fma(-2 x~_i, x~_j,
+//     n~_j))) < fl32(thr - n~_i), i.e. |x~_i - x~_j|^2 < thr, three FMAs per candidate.  thr
+//     exceeds r_c^2 by a proven bound on the FP32 rounding (lj_guard_threshold), so the listed
+//     pairs are a superset of the pairs inside the cutoff; pass 2 takes the exact FP64 decision.
+// Pass 2 (when a list could overflow, and at the end): the lanes of each molecule copy their lists
+// into one list per molecule (slices in order), then lane (i, s) evaluates its entries s, s + NS,
+// ... in order: the molecule's hits split evenly over its lanes.  Each pair is evaluated from the
+// exact FP64 separation (staged FP64 positions): the energy always in FP64 (from the FP32
+// reciprocal refined by one FP64 Newton step on the FP32 path), the force scalar, force and
+// virial in R.  FP32 sums of one flush are promoted to the lane's FP64 sums at its end.
+// A block whose tile exceeds the LDS capacity walks the same candidates in the same order through
+// per-wavefront windows of its segments: the same pairs, each evaluated the same way; only the
+// points where lists are flushed can differ (a window change flushes), which regroups each
+// molecule's sum over its lanes: a difference of rounding.  Slice sums are combined through LDS in
+// a fixed order.  Home cells with more than 64 molecules use lj1_cell_chunked (a decision fixed by
+// the configuration, not by the capacity).
 constexpr int QCELLS = 48;  // 3 x 4 x 4 staged cells
 constexpr int NSMAX = 8;
+constexpr int SLACK = 32;  // spare tile entries read (never counted) past the end of a walk
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// LJ constants of the single-site kernels: FP64 model values, their FP32 roundings for the FP32
+// force scalar, and the FP32 pass-1 threshold.
+struct LJK {
+  double eps4, eps24, sig2, shift, rc2;
+  float eps24f, sig2f, thr;
+};
+
+// Sums of one flush of one lane: force and virial diagonal in R, energy in FP64, partner count.
+template <typename R> struct LJFlush {
+  R fx = 0, fy = 0, fz = 0, wx = 0, wy = 0, wz = 0;
+  double u = 0.0;
+  int n = 0;
+};
+
+// One listed partner at the exact FP64 separation d.
+template <typename R>
+__device__ __forceinline__ void lj_hit(LJFlush<R> &a, double dx, double dy, double dz, const LJK &k) {
+  const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  if constexpr (std::is_same<R, float>::value) {
+    if (!(r2 < k.rc2)) return;  // listed by the FP32 test, outside the exact cutoff
+    const float y = __builtin_amdgcn_rcpf((float)r2);
+    // energy: 1/r^2 refined to FP64 accuracy by one FP64 Newton step from the FP32 seed
+    const double yd = fma((double)y, fma(-r2, (double)y, 1.0), (double)y);
+    const double s2 = k.sig2 * yd, s6 = s2 * s2 * s2;
+    a.u = fma(k.eps4 * s6, s6 - 1.0, a.u);
+    // force scalar from the FP32 seed (1 ulp), force and virial in FP32
+    const float t2 = k.sig2f * y, t6 = t2 * t2 * t2;
+    const float fs = (k.eps24f * y) * (t6 * fmaf(2.0f, t6, -1.0f));
+    const float ex = (float)dx, ey = (float)dy, ez = (float)dz;
+    const float gx = fs * ex, gy = fs * ey, gz = fs * ez;
+    a.fx += gx, a.fy += gy, a.fz += gz;
+    a.wx = fmaf(gx, ex, a.wx), a.wy = fmaf(gy, ey, a.wy), a.wz = fmaf(gz, ez, a.wz);
+  } else {
+    const double y = rcp_nr<double>(r2);
+    const double s2 = k.sig2 * y, s6 = s2 * s2 * s2;
+    a.u = fma(k.eps4 * s6, s6 - 1.0, a.u);
+    const double fs = (k.eps24 * y) * (s6 * fma(2.0, s6, -1.0));
+    const double gx = fs * dx, gy = fs * dy, gz = fs * dz;
+    a.fx += gx, a.fy += gy, a.fz += gz;
+    a.wx = fma(gx, dx, a.wx), a.wy = fma(gy, dy, a.wy), a.wz = fma(gz, dz, a.wz);
+  }
+  a.n += 1;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double rc2, PairOut o, int cap, int lcap) {
+__global__ __launch_bounds__(256) void k_pair_lj(CellsDev c, LJK k, PairOut o, int cap, int lcap) {
+  constexpr bool F32 = std::is_same<R, float>::value;
   extern __shared__ double dyn[];
-  // staged positions, x y z interleaved: entry t at tp[3 t .. 3 t + 2]
-  double *tp = dyn;
-  // the same memory as an LDS-qualified pointer, so indexing stays 32-bit
-  __attribute__((address_space(3))) double *lds = (__attribute__((address_space(3))) double *)dyn;
-  unsigned short *list = (unsigned short *)(dyn + 3 * cap);
+  // LDS: [FP32 tile: cap float4 (FP32 path)] [FP64 tile: cap x 3 doubles] [per-lane lists: 256 x
+  // lcap]; list entries are staged slots (16 bit)
+  f4v *const t32 = (f4v *)dyn;
+  double *const t64 = dyn + (F32 ? 2 * cap : 0);
+  __attribute__((address_space(3))) f4v *const l32 = (__attribute__((address_space(3))) f4v *)t32;
+  __attribute__((address_space(3))) double *const l64 = (__attribute__((address_space(3))) double *)t64;
+  unsigned short *const lists = (unsigned short *)(t64 + 3 * cap);
   __shared__ int qoff[QCELLS + 1], qstart[QCELLS];
   __shared__ double qsh[QCELLS][3];
-  __shared__ int scnt[4][64];
   __shared__ double red[4][5];
   // neighbour table of the chunked path, in the (then unused) list area
-  NbTable &nb = *(NbTable *)list;
+  NbTable &nb = *(NbTable *)lists;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nby = (c.ny + 1) >> 1, nbz = (c.nz + 1) >> 1;
@@ -239,6 +307,19 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
     }
     __syncthreads();
     const int U = qoff[QCELLS];
+    // tile centre: origin of the FP32 coordinates
+    const double ox = (bx + 0.5) * c.hx, oy = (2 * by + 1) * c.hy, oz = (2 * bz + 1) * c.hz;
+    // stage entry: FP64 shifted position (x, y, z) at slot e, FP32 centre-relative copy and norm
+    auto put = [&](int e, double x, double y, double z) {
+      t64[3 * e] = x, t64[3 * e + 1] = y, t64[3 * e + 2] = z;
+      if constexpr (F32) {
+        const float fx = (float)(x - ox), fy = (float)(y - oy), fz = (float)(z - oz);
+        t32[e] = f4v{fx, fy, fz, fmaf(fz, fz, fmaf(fy, fy, fx * fx))};
+      }
+    };
+    auto stage = [&](int e, int src, int cc) {
+      put(e, c.sx[src] + qsh[cc][0], c.sy[src] + qsh[cc][1], c.sz[src] + qsh[cc][2]);
+    };
     // this wavefront's home cell: tile cell uh (unshifted, since it lies inside the box)
     const int hy = wave & 1, hz = wave >> 1;
     const bool hvalid = 2 * by + hy < c.ny && 2 * bz + hz < c.nz;
@@ -246,14 +327,14 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
     const int hn = hvalid ? __builtin_amdgcn_readfirstlane(qoff[uh + 1] - qoff[uh]) : 0;
     const int hs = qstart[uh];
     if (!__syncthreads_or(hn > 64)) {
-      // the walk reads up to 2 NS - 1 <= 15 entries past a segment (results discarded), so the
+      // the walk reads up to 4 NS - 1 <= 31 entries past a segment (results discarded), so the
       // tile needs that much slack
-      const bool tiled = U + 16 <= cap;  // block-uniform
-      // the permutation entry of this lane's home molecule, needed only at the end
+      const bool tiled = U + SLACK <= cap;  // block-uniform
       const int orig32 = lane < hn ? c.perm[hs + lane] : 0;
       if (tiled) {
         // stage by x-rows of three cells (contiguous in the sorted arrays unless x wraps): wave w
-        // takes rows w, w + 4, w + 8, w + 12, first entries of all four rows loaded together
+        // takes rows w, w + 4, w + 8, w + 12, the first 64 entries of all four rows loaded
+        // before any is stored (one round of global-load latency), longer rows after
         double vx[4], vy[4], vz[4];
         int dst[4];
 #pragma unroll
@@ -270,84 +351,76 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (dst[q] >= 0) tp[3 * dst[q]] = vx[q], tp[3 * dst[q] + 1] = vy[q], tp[3 * dst[q] + 2] = vz[q];
-        for (int q = 0; q < 4; ++q) {  // rows longer than 64 entries
+          if (dst[q] >= 0) put(dst[q], vx[q], vy[q], vz[q]);
+        for (int q = 0; q < 4; ++q) {
           const int u = 3 * (wave + 4 * q);
           for (int e = qoff[u] + 64 + lane; e < qoff[u + 3]; e += 64) {
             const int cc = e < qoff[u + 1] ? u : (e < qoff[u + 2] ? u + 1 : u + 2);
-            const int src = qstart[cc] + (e - qoff[cc]);
-            tp[3 * e] = c.sx[src] + qsh[cc][0], tp[3 * e + 1] = c.sy[src] + qsh[cc][1];
-            tp[3 * e + 2] = c.sz[src] + qsh[cc][2];
+            stage(e, qstart[cc] + (e - qoff[cc]), cc);
           }
         }
         __syncthreads();
       }
-      LJAcc<R> a;
       const float rhn = __builtin_amdgcn_rcpf((float)(hn > 0 ? hn : 1));
       const int NS = hn > 0 ? min(NSMAX, div_small(64, rhn)) : 1;
       const int sl = hn > 0 ? div_small(lane, rhn) : NS, il = hn > 0 ? lane - sl * hn : 0;
-      const float rns = __builtin_amdgcn_rcpf((float)NS), r2ns = 0.5f * rns;  // 1/NS, 1/(2 NS)
+      const float r2ns = 0.5f * __builtin_amdgcn_rcpf((float)NS);  // 1/(2 NS)
       const bool act = sl < NS;
+      // FP64 sums of this lane over all flushes
+      double sfx = 0.0, sfy = 0.0, sfz = 0.0, su = 0.0, swx = 0.0, swy = 0.0, swz = 0.0;
+      int sn = 0;
       if (hn > 0) {
         const int self = qoff[uh] + il;
-        double xi = 1e30, yi = 1e30, zi = 1e30;  // idle lanes: no candidate is within the cutoff
+        // this lane's molecule: FP64 position, FP32 test operands (idle lanes: far away)
+        double xi = 1e30, yi = 1e30, zi = 1e30;
+        float ax = 0.0f, ay = 0.0f, az = 0.0f, thri = -1.0f;
         if (act) {
-          if (tiled) xi = tp[3 * self], yi = tp[3 * self + 1], zi = tp[3 * self + 2];
+          if (tiled) xi = t64[3 * self], yi = t64[3 * self + 1], zi = t64[3 * self + 2];
           else xi = c.sx[hs + il], yi = c.sy[hs + il], zi = c.sz[hs + il];
+          if constexpr (F32) {
+            const float fx = (float)(xi - ox), fy = (float)(yi - oy), fz = (float)(zi - oz);
+            ax = -2.0f * fx, ay = -2.0f * fy, az = -2.0f * fz;
+            thri = k.thr - fmaf(fz, fz, fmaf(fy, fy, fx * fx));
+          }
         }
-        unsigned short *wlist = list + (size_t)wave * 64 * lcap;
-        const R eps24 = (R)p.eps24, sig2 = (R)p.sig2;
-        // staged positions: the whole tile (slot = tile index) or this wavefront's window of cq
+        const double rc2 = k.rc2;
+        unsigned short *const wlist = lists + (size_t)wave * 64 * lcap;
+        // staged slots: the whole tile (slot = tile index) or this wavefront's window of cq
         // entries, of which the first C are staged at a time
-        const int cq = (cap - 16) >> 2;
-        const int C = div_small(cq - 16, r2ns) * (2 * NS);
-        const int wb = tiled ? 0 : 3 * wave * cq;  // index into dyn of staged slot 0 (32-bit LDS math)
-        // this lane's hit list: entry k at mylist[64 k], holding the LDS index (in doubles) of the
-        // staged candidate; lp is the next free entry
+        const int cq = (cap - SLACK) >> 2;
+        const int C = div_small(cq - SLACK, r2ns) * (2 * NS);
+        const int wb = tiled ? 0 : wave * cq;  // slot of window entry 0
+        // this lane's hit list: entry k at mylist[64 k]; lp is the next free entry
         __attribute__((address_space(3))) unsigned short *const mylist =
             (__attribute__((address_space(3))) unsigned short *)wlist + lane;
         __attribute__((address_space(3))) unsigned short *lp = mylist;
         __attribute__((address_space(3))) unsigned short *const lplim = mylist + 64 * (lcap - 2);
-        // pass 2: the hits of a molecule (its NS lanes' lists, in slice order) are split into NS
-        // contiguous equal parts, one per lane; each lane sums its part in order
+        // pass 2: every lane evaluates its own list in order.  (Splitting each molecule's hits
+        // evenly over its lanes evens out their counts but needs a buffer per molecule, and the
+        // LDS it takes costs a resident block per CU, more than the balance gains.)
+        // FP64 path: one set of FP64 sums for the whole walk; FP32 path: FP32 sums per flush,
+        // promoted to the lane's FP64 sums (cascaded summation)
+        LJFlush<double> a64;
         auto flush = [&]() {
           const int cnt = (int)(lp - mylist) >> 6;
-          scnt[wave][lane] = cnt;
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           if (act) {
-            unsigned H = 0;
-#pragma unroll
-            for (int s2 = 0; s2 < NSMAX; ++s2)
-              if (s2 < NS) H += (unsigned)scnt[wave][il + s2 * hn];
-            const unsigned q0 = (unsigned)div_small((int)H * sl, rns), q1 = (unsigned)div_small((int)H * (sl + 1), rns);
-            if (q0 < q1) {
-              // locate hit q0: list sp, entry j
-              unsigned j = q0;
-              int sp = 0;
-              unsigned csp = (unsigned)scnt[wave][il];
-              while (j >= csp) j -= csp, ++sp, csp = (unsigned)scnt[wave][il + sp * hn];
-              int li = il + sp * hn + 64 * (int)j;
-              int iu = wlist[li];
-              for (unsigned q = q0; q < q1; ++q) {
-                const int cu = iu;
-                const double dx = xi - lds[cu], dy = yi - lds[cu + 1], dz = zi - lds[cu + 2];
-                // next hit: same list, or the first entry of the next non-empty list
-                if (q + 1 < q1) {
-                  ++j, li += 64;
-                  while (j >= csp) j = 0, ++sp, csp = (unsigned)scnt[wave][il + sp * hn], li = il + sp * hn;
-                  iu = wlist[li];
-                }
-                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                a.add(dx, dy, dz, r2, eps24, sig2, p.eps4, p.sig2);
+            if constexpr (F32) {
+              LJFlush<float> a;
+              for (int q = 0; q < cnt; ++q) {
+                const int e = mylist[64 * q];
+                lj_hit<float>(a, xi - l64[3 * e], yi - l64[3 * e + 1], zi - l64[3 * e + 2], k);
+              }
+              sfx += (double)a.fx, sfy += (double)a.fy, sfz += (double)a.fz;
+              swx += (double)a.wx, swy += (double)a.wy, swz += (double)a.wz;
+              su += a.u, sn += a.n;
+            } else {
+              for (int q = 0; q < cnt; ++q) {
+                const int e = mylist[64 * q];
+                lj_hit<double>(a64, xi - l64[3 * e], yi - l64[3 * e + 1], zi - l64[3 * e + 2], k);
               }
             }
           }
           lp = mylist;
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         };
         const int sla = act ? sl : 0;  // idle lanes walk with slice 0
         for (int d = 0; d < 3; ++d) {
@@ -355,42 +428,57 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
           const int lo = __builtin_amdgcn_readfirstlane(qoff[u0]), hi = __builtin_amdgcn_readfirstlane(qoff[u0 + 9]);
           for (int cs = lo, ce; cs < hi; cs = ce) {
             ce = tiled ? hi : min(hi, cs + C);
-            const int off = tiled ? 0 : cs;
+            const int off = tiled ? 0 : cs - wb;  // slot = tile index - off
             if (!tiled) {
               // stage [cs, ce) of this segment into the window; the previous window is flushed
               flush();
-              for (int k = cs + lane; k < ce; k += 64) {
+              for (int e = cs + lane; e < ce; e += 64) {
                 int u = u0;
-                while (k >= qoff[u + 1]) ++u;
-                const int src = qstart[u] + (k - qoff[u]);
-                double *e = dyn + wb + 3 * (k - cs);
-                e[0] = c.sx[src] + qsh[u][0];
-                e[1] = c.sy[src] + qsh[u][1];
-                e[2] = c.sz[src] + qsh[u][2];
+                while (e >= qoff[u + 1]) ++u;
+                stage(e - off, qstart[u] + (e - qoff[u]), u);
               }
-              __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-              __builtin_amdgcn_wave_barrier();
-              __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+              wave_sync_lds();
             }
             // two candidates per iteration, both loaded before either is tested.  Only the last
             // iteration can pass the end of the range (its extra slots are read, never counted),
             // and only the home layer holds the molecule itself.
+            // slice s tests the adjacent slots 2 s, 2 s + 1 of every run of 2 NS candidates; the
+            // pair of the next run is loaded before the current one is tested (the walk reads up
+            // to 4 NS - 1 slots past the range: the tile keeps SLACK spare entries)
             auto walk = [&](auto tail, auto home) {
-              int ia = wb + 3 * (cs + sla - off);  // running LDS index of candidate a
-              for (int kb = cs; tail ? kb < ce : kb + 2 * NS <= ce; kb += 2 * NS, ia += 6 * NS) {
-                const int ta = kb + sla, tb = ta + NS;
-                const int ib = ia + 3 * NS;
-                const double ax = xi - lds[ia], ay = yi - lds[ia + 1], az = zi - lds[ia + 2];
-                const double bx_ = xi - lds[ib], by_ = yi - lds[ib + 1], bz_ = zi - lds[ib + 2];
-                const double ra = fma(az, az, fma(ay, ay, ax * ax));
-                const double rb = fma(bz_, bz_, fma(by_, by_, bx_ * bx_));
-                bool ha = ra < rc2, hb = rb < rc2;
-                if (tail) ha = ha && ta < ce, hb = hb && tb < ce;
-                if (home) ha = ha && ta != self, hb = hb && tb != self;
+              int sa = cs + 2 * sla - off;  // slot of this lane's first candidate
+              const int send = ce - off, sself = self - off;
+              using V = typename std::conditional<F32, f4v, double>::type;
+              V a0, a1, a2, b0, b1, b2;
+              auto load = [&](int t) {
+                if constexpr (F32) {
+                  a0 = l32[t], b0 = l32[t + 1];
+                } else {
+                  a0 = l64[3 * t], a1 = l64[3 * t + 1], a2 = l64[3 * t + 2];
+                  b0 = l64[3 * t + 3], b1 = l64[3 * t + 4], b2 = l64[3 * t + 5];
+                }
+              };
+              load(sa);
+              for (int kb = cs; tail ? kb < ce : kb + 2 * NS <= ce; kb += 2 * NS, sa += 2 * NS) {
+                bool ha, hb;
+                if constexpr (F32) {
+                  const f4v qa = a0, qb = b0;
+                  if (!tail) load(sa + 2 * NS);
+                  ha = fmaf(az, qa.z, fmaf(ay, qa.y, fmaf(ax, qa.x, qa.w))) < thri;
+                  hb = fmaf(az, qb.z, fmaf(ay, qb.y, fmaf(ax, qb.x, qb.w))) < thri;
+                } else {
+                  const double pax = xi - a0, pay = yi - a1, paz = zi - a2;
+                  const double pbx = xi - b0, pby = yi - b1, pbz = zi - b2;
+                  if (!tail) load(sa + 2 * NS);
+                  ha = fma(paz, paz, fma(pay, pay, pax * pax)) < rc2;
+                  hb = fma(pbz, pbz, fma(pby, pby, pbx * pbx)) < rc2;
+                }
+                if (tail) ha = ha && sa < send, hb = hb && sa + 1 < send;
+                if (home) ha = ha && sa != sself, hb = hb && sa + 1 != sself;
                 // the slot is always written; the count advances on a hit
-                *lp = (unsigned short)ia;
+                *lp = (unsigned short)sa;
                 lp += ha ? 64 : 0;
-                *lp = (unsigned short)ib;
+                *lp = (unsigned short)(sa + 1);
                 lp += hb ? 64 : 0;
                 if (__any(lp > lplim)) flush();
                 if (tail) break;
@@ -409,14 +497,18 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
           }
         }
         flush();
+        if constexpr (!F32) {
+          sfx = a64.fx, sfy = a64.fy, sfz = a64.fz, swx = a64.wx, swy = a64.wy, swz = a64.wz;
+          su = a64.u, sn = a64.n;
+        }
       }
       // combine the slices of each molecule in a fixed order through LDS (the tile is free now)
       __syncthreads();
       double *sred = dyn + (size_t)wave * 64 * 8;
       if (act) {
         double *e = sred + lane;  // [quantity][lane]: consecutive lanes, distinct banks
-        e[0] = a.fx, e[64] = a.fy, e[128] = a.fz, e[192] = a.u, e[256] = a.wx, e[320] = a.wy, e[384] = a.wz;
-        e[448] = (double)a.n;
+        e[0] = sfx, e[64] = sfy, e[128] = sfz, e[192] = su, e[256] = swx, e[320] = swy, e[384] = swz;
+        e[448] = (double)sn;
       }
       __syncthreads();
       if (lane < hn) {
@@ -425,7 +517,7 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
         for (int s = 1; s < NS; ++s)
           for (int q = 0; q < 8; ++q) v[q] += sred[q * 64 + lane + s * hn];
         const double nn = v[7];
-        const double u = v[3] - nn * p.shift;
+        const double u = v[3] - nn * k.shift;
         const int64_t orig = orig32;  // 64-bit: 3 orig exceeds 2^31 beyond 7e8 molecules
         o.force[3 * orig] = v[0], o.force[3 * orig + 1] = v[1], o.force[3 * orig + 2] = v[2];
         if (o.torque) o.torque[3 * orig] = 0.0, o.torque[3 * orig + 1] = 0.0, o.torque[3 * orig + 2] = 0.0;
@@ -435,10 +527,11 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
         acc5[0] = 0.5 * u, acc5[1] = 0.5 * v[4], acc5[2] = 0.5 * v[5], acc5[3] = 0.5 * v[6], acc5[4] = nn;
       }
     } else {
+      const LJPair p{k.eps4, k.eps24, k.sig2, k.shift, 0.0, 0.0, 0.0, 0.0};
       for (int w = 0; w < 4; ++w) {
         const int fy = 2 * by + (w & 1), fz = 2 * bz + (w >> 1);
         if (fy < c.ny && fz < c.nz)
-          lj1_cell_chunked<R>(c, p, rc2, o, (fz * c.ny + fy) * c.nx + bx, dyn, dyn + cap, dyn + 2 * cap, cap, nb,
+          lj1_cell_chunked<R>(c, p, k.rc2, o, (fz * c.ny + fy) * c.nx + bx, dyn, dyn + cap, dyn + 2 * cap, cap, nb,
                               acc5);
       }
     }
@@ -446,9 +539,30 @@ __global__ __launch_bounds__(256) void k_pair_lj1(CellsDev c, LJPair p, double r
   write_partial_block<4>(o.partial, acc5, red);
 }
 
+// Threshold of the FP32 cutoff test of k_pair_lj: every pair with (FP64) r^2 < r_c^2 passes
+// T < fl32(thr - n~_i).  With u = 2^-24 and rho = (1.5 h_x, 2 h_y, 2 h_z) the largest offset of a
+// staged position from the tile centre, R = |rho|:
+//   * stored coordinates x~ = fl32(x - o) differ from x - o by at most u rho_k per axis, so the
+//     FP32 separation a - b is within 2 u R of the exact one and |a - b|^2 <= r^2 + 4 u R r_c +
+//     4 u^2 R^2 near the cutoff;
+//   * n~ = fl32(|x~|^2) by two FMAs and a product: error <= 3.01 u R^2; the three FMAs of T round
+//     partial sums of magnitude <= 3 R^2: error <= 9 u R^2; fl32(thr - n~_i) loses <= u (thr + R^2);
+// so T < fl32(thr - n~_i) holds whenever thr (1 - u) > r_c^2 (1 + 2^-51) + 4 u R r_c + 16.02 u R^2 +
+// 4 u^2 R^2.  thr = (r_c^2 + 4 u R r_c + 17 u R^2)(1 + 2 u), rounded up to FP32, satisfies it with
+// margin; at r_c = 2.5, h = 2.54 it exceeds r_c^2 by 1.3e-5 relative, so pass 2 rejects about
+// 1e-4 listed candidates per molecule.
+inline float lj_guard_threshold(double rc, double hx, double hy, double hz) {
+  const double u = 0x1p-24;
+  const double R = std::sqrt(2.25 * hx * hx + 4.0 * hy * hy + 4.0 * hz * hz) * (1.0 + 1e-12);
+  const double thr = (rc * rc + 4.0 * u * R * rc + 17.0 * u * R * R) * (1.0 + 2.0 * u);
+  float t = (float)thr;
+  if ((double)t < thr) t = std::nextafter(t, INFINITY);
+  return t;
+}
+
 // Staged-partner capacity of the LJ tile: the 48 tile cells at 1.12 x the mean occupancy + 32,
 // rounded up to 32, within [256, 4096]; denser tiles take the windowed walk.  (List entries are
-// 16-bit LDS indices of staged entries, 3 per entry, so 3 x 4096 stays below 65536.)
+// 16-bit staged slots.)
 inline int lj1_tile_cap(int64_t N, int64_t ncell) {
   const double mean = (double)N / (double)ncell;
   int cap = (int)(QCELLS * mean * 1.12) + 32;
@@ -1226,11 +1340,15 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
                : launch_ms<double, 1, 0, 0, 0, false, 96, 256, 3>(cd, m, o, nb, mean, s);
   }
   if (m->single_site) {
-    const LJPair p = m->host.lj[0][0][0][0];
-    int cap = std::max(lj1_tile_cap(c->N, c->ncell), 256 * 8 / 3 + 1);
+    const LJPair &p = m->host.lj[0][0][0][0];
+    const LJK k{p.eps4, p.eps24, p.sig2, p.shift, m->host.rc2, (float)p.eps24, (float)p.sig2,
+                lj_guard_threshold(m->host.rc, cd.hx, cd.hy, cd.hz)};
+    int cap = lj1_tile_cap(c->N, c->ncell);
     int lcap = lj1_list_cap(c->N, c->box[0] * c->box[1] * c->box[2], m->host.rc, c->ncell);
-    auto dyn_lds = [](int cp, int lc) {
-      return std::max((size_t)cp * 3 * sizeof(double), (size_t)256 * 8 * sizeof(double)) +
+    // tile (FP32 copy on the FP32 path, FP64 positions; at least the 16 KiB of the slice sums),
+    // then per-lane and per-molecule hit lists
+    auto dyn_lds = [f32](int cp, int lc) {
+      return std::max((size_t)cp * (f32 ? 40 : 24), (size_t)256 * 8 * sizeof(double)) +
              (size_t)lc * 256 * sizeof(unsigned short);
     };
     // stay within the device's LDS per block: shrink the tile first (tiles beyond it take the
@@ -1245,18 +1363,18 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
     }
     if (m->lj1_static_lds[f32] < 0) {
       hipFuncAttributes fa{};
-      const void *k = f32 ? (const void *)k_pair_lj1<float> : (const void *)k_pair_lj1<double>;
-      m->lj1_static_lds[f32] = hipFuncGetAttributes(&fa, k) == hipSuccess ? (int)fa.sharedSizeBytes : 4096;
+      const void *kf = f32 ? (const void *)k_pair_lj<float> : (const void *)k_pair_lj<double>;
+      m->lj1_static_lds[f32] = hipFuncGetAttributes(&fa, kf) == hipSuccess ? (int)fa.sharedSizeBytes : 4096;
     }
     const size_t stat = (size_t)m->lj1_static_lds[f32];
-    while (stat + dyn_lds(cap, lcap) > (size_t)m->lds_limit && cap > 683) cap = std::max(683, cap - 64);
+    while (stat + dyn_lds(cap, lcap) > (size_t)m->lds_limit && cap > 256) cap = std::max(256, cap - 64);
     while (stat + dyn_lds(cap, lcap) > (size_t)m->lds_limit && lcap > 16) lcap -= 4;
     const size_t lds = dyn_lds(cap, lcap);
     const int64_t nq = pair_blocks((int64_t)c->nc[0] * ((c->nc[1] + 1) / 2) * ((c->nc[2] + 1) / 2));
     *nblocks = nq;
-    if (f32) k_pair_lj1<float><<<(unsigned)nq, 256, lds, s>>>(cd, p, m->host.rc2, o, cap, lcap);
-    else k_pair_lj1<double><<<(unsigned)nq, 256, lds, s>>>(cd, p, m->host.rc2, o, cap, lcap);
-    return check_hip(hipGetLastError(), "k_pair_lj1");
+    if (f32) k_pair_lj<float><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap);
+    else k_pair_lj<double><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap);
+    return check_hip(hipGetLastError(), "k_pair_lj");
   }
   const Shape &S = m->shape;
   const double mean = (double)c->N / (double)c->ncell;

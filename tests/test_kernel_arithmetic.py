@@ -4,6 +4,7 @@ with the reciprocal anywhere within 1 ulp of 1/b, as the hardware instruction gu
 the exact integer sums of the half-shell pair kernel's partner terms (modular uint64 arithmetic:
 wrap-around is intended)."""
 import numpy as np
+import pytest
 
 
 def test_small_division_through_fp32_reciprocal():
@@ -89,3 +90,62 @@ def test_two_word_sum_with_32_bit_high_word():
     low = (_bits(x + M) & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.int32).astype(np.int64)
     np.testing.assert_array_equal(low, np.rint(x).astype(np.int64))
     assert abs(int(low.sum())) < 2 ** 31
+
+
+# ---------------------------------------------------------------- FP32 cutoff test of the LJ kernel
+# The single-site pair kernel lists candidate j for molecule i when
+#   T = fma(-2 z~_i, z~_j, fma(-2 y~_i, y~_j, fma(-2 x~_i, x~_j, n~_j))) < fl32(thr - n~_i),
+# x~ = fl32(x - o) relative to the tile centre o, n~ = fma(z~, z~, fma(y~, y~, x~ * x~)) in FP32,
+# and decides exactly in FP64 afterwards.  The threshold below (the kernel's bound, restated)
+# must let every pair with FP64 r^2 < r_c^2 through.  Emulation: FP32 values held in float64,
+# each FMA as the exact product plus the addend rounded once to float64, then once to float32
+# (the float64 step can differ from a fused FP32 FMA by a rounding of 2^-53 relative, far below
+# the margins measured here).
+
+def _guard_threshold(rc, hx, hy, hz):
+    u = 2.0 ** -24
+    R = np.sqrt(2.25 * hx * hx + 4.0 * hy * hy + 4.0 * hz * hz) * (1.0 + 1e-12)
+    thr = (rc * rc + 4.0 * u * R * rc + 17.0 * u * R * R) * (1.0 + 2.0 * u)
+    t = np.float32(thr)
+    if float(t) < thr:
+        t = np.nextafter(t, np.float32(np.inf))
+    return t
+
+
+def _f32(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def _fma32(a, b, c):
+    return _f32(a * b + c)
+
+
+@pytest.mark.parametrize("rc,h", [(2.5, 2.5413249), (3.0, 3.0097), (2.5, 2.8499600), (2.5, 3.7), (6.0, 6.2)])
+def test_fp32_cutoff_threshold_never_drops_a_pair(rc, h):
+    rng = np.random.default_rng(int(rc * 1000 + h * 10))
+    n = 200000
+    thr = float(_guard_threshold(rc, h, h, h))
+    o = rng.uniform(0.0, 50.0, size=3)
+    # i anywhere in the tile's home region, j at a distance just inside (or at) the cutoff in a
+    # random direction, clipped to the staged extent (1.5 h in x, 2 h in y and z from o)
+    ext = np.array([1.5 * h, 2.0 * h, 2.0 * h])
+    xi = o + rng.uniform(-0.5, 0.5, size=(n, 3)) * np.array([h, 2 * h, 2 * h])
+    v = rng.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    r = rc * (1.0 - rng.uniform(0.0, 1e-6, size=n) * rng.choice([1e-9, 1e-6, 1e-3, 1.0], size=(n,)))
+    xj = xi - r[:, None] * v
+    keep = np.all(np.abs(xj - o) <= ext, axis=1)
+    xi, xj = xi[keep], xj[keep]
+    d = xi - xj
+    r2 = d[:, 2] * d[:, 2] + (d[:, 1] * d[:, 1] + d[:, 0] * d[:, 0])  # near-exact; ties decided below
+    inside = r2 < rc * rc
+    a, b = _f32(xi - o), _f32(xj - o)
+    nj = _fma32(b[:, 2], b[:, 2], _fma32(b[:, 1], b[:, 1], _f32(b[:, 0] * b[:, 0])))
+    ni = _fma32(a[:, 2], a[:, 2], _fma32(a[:, 1], a[:, 1], _f32(a[:, 0] * a[:, 0])))
+    T = _fma32(-2.0 * a[:, 2], b[:, 2], _fma32(-2.0 * a[:, 1], b[:, 1], _fma32(-2.0 * a[:, 0], b[:, 0], nj)))
+    thri = _f32(thr - ni)
+    assert inside.sum() > 1000
+    margin = (thri - T)[inside]
+    assert np.all(margin > 0.0), f"a pair inside the cutoff fails the FP32 test (min margin {margin.min()})"
+    # the threshold stays close to r_c^2: few extra pairs reach the exact test
+    assert thr / (rc * rc) - 1.0 < 1e-4
