@@ -110,7 +110,8 @@ typedef struct md_model md_model; /* opaque: device copy of the model tables + s
 typedef struct md_cells md_cells; /* opaque: cell grid + molecules sorted into cells */
 
 /* Read-only view of a built cell grid (device pointers owned by the md_cells object, valid until
- * the next md_build_cells / md_cells_destroy on it).  Cells have edge h_k = L_k / n_k > r_c,
+ * the next md_build_cells / md_cells_destroy on it).  md_cells_view forms cell_of on the device
+ * on its first call after a build (syncs the model's last stream).  Cells have edge h_k = L_k / n_k > r_c,
  * n_k = floor(L_k / r_c) reduced until h_k >= r_c (1 + 2^-30); linear cell id
  * (c_z n_y + c_y) n_x + c_x.  Molecules are sorted stably by cell: within a cell by original
  * index. */

@@ -359,7 +359,8 @@ int md_cells_create(md_cells **out) {
 
 int md_cells_destroy(md_cells *c) {
   if (!c) return MD_OK;
-  dfree(c->cell_of), dfree(c->slot), dfree(c->tmp), dfree(c->perm), dfree(c->perm_prev), dfree(c->scomp);
+  dfree(c->cell_of), dfree(c->cellv), dfree(c->slot), dfree(c->tmp), dfree(c->perm), dfree(c->perm_prev);
+  dfree(c->scomp);
   dfree(c->count), dfree(c->start), dfree(c->bsum), dfree(c->lstart);
   dfree(c->sx), dfree(c->sy), dfree(c->sz), dfree(c->svec), dfree(c->squat);
   delete c;
@@ -369,6 +370,14 @@ int md_cells_destroy(md_cells *c) {
 int md_cells_view(const md_cells *c, md_cells_info *out) {
   if (!c || !out) return set_error(MD_EINVAL, "md_cells_view: NULL argument");
   if (!c->built) return set_error(MD_EINVAL, "md_cells_view: cells not built");
+  if (!c->cell_of_valid) {  // the caller-order cell ids, formed once per build on request
+    md_cells *cm = const_cast<md_cells *>(c);
+    const hipStream_t s = c->model ? c->model->last_stream : nullptr;
+    int rc = launch_cell_of(c, s);
+    if (!rc) rc = check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (rc) return rc;
+    cm->cell_of_valid = true;
+  }
   out->N = c->N;
   out->ncell = c->ncell;
   for (int k = 0; k < 3; ++k) out->nc[k] = c->nc[k], out->box[k] = c->box[k];
@@ -403,7 +412,8 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
   const bool reuse_order = c->built && c->N == N && N <= capN;
   if (N > capN) {
     int64_t cap = 0;
-    if ((rc = grow(c->cell_of, cap, N, "cell_of")) || (cap = 0, rc = grow(c->slot, cap, N, "slot")) ||
+    if ((rc = grow(c->cell_of, cap, N, "cell_of")) || (cap = 0, rc = grow(c->cellv, cap, N, "cellv")) ||
+        (cap = 0, rc = grow(c->slot, cap, N, "slot")) ||
         (cap = 0, rc = grow(c->tmp, cap, N, "tmp")) || (cap = 0, rc = grow(c->perm, cap, N, "perm")) ||
         (cap = 0, rc = grow(c->perm_prev, cap, N, "perm")) ||
         (cap = 0, rc = grow(c->scomp, cap, N, "scomp")) || (cap = 0, rc = grow(c->sx, cap, N, "sx")) ||
@@ -453,6 +463,8 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
   rc = launch_build(m, c, pos, quat, m->host.ncomp > 1 ? comp : nullptr, N, inv_h, order, s);
   prof_end(m, PROF_BUILD, s, ev);
   if (rc) return rc;
+  c->order = order;
+  c->cell_of_valid = false;
   c->built = true;
   return sync_check(m, s);
 }

@@ -22,19 +22,21 @@ __device__ __forceinline__ int bin1(double xw, double inv_h, int n) {
 
 struct BinArgs {
   const double *pos, *quat;
-  const int32_t *comp, *order;  // order: processing order (the previous build's permutation) or NULL
+  const int32_t *comp, *order;  // order: visiting order (the previous build's permutation) or NULL
   int64_t N;
   double Lx, Ly, Lz, ihx, ihy, ihz;
   int32_t nx, ny, nz, ncomp, check_quat;
-  int32_t *cell_of, *slot, *count, *status;
+  int32_t *cellv, *slotv, *count, *status;
 };
 
-// Wrap + bin + per-cell histogram.  Thread d takes molecule order[d] (identity without an order):
-// with the previous build's permutation, neighbouring threads mostly fall into the same cell, and
-// each run of equal cells inside a wavefront takes one atomic add.  The slot it returns is only a
-// provisional position; the final order inside a cell is fixed by k_rank_gather.
+// Wrap + bin + per-cell histogram.  Position d of the visiting order takes molecule order[d]
+// (identity without an order) and writes its cell and provisional slot at position d (coalesced).
+// In the previous build's order neighbouring positions mostly fall into the same cell, and each
+// run of equal cells inside a wavefront takes one atomic add.  The blocks of each XCD (block b
+// runs on XCD b % 8) take one contiguous eighth of the positions, so the COM lines a region of
+// space gathers meet in one L2.  The final order inside a cell is fixed by k_rank_gather.
 __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
-  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t d = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const bool valid = d < a.N;
   const int64_t i = valid ? (a.order ? (int64_t)a.order[d] : d) : 0;
@@ -74,8 +76,8 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
   if (head && valid) base = atomicAdd(a.count + cell, next - lane);
   base = __shfl(base, hl, 64);
   if (valid) {
-    a.cell_of[i] = cell;
-    a.slot[i] = base + (lane - hl);
+    a.cellv[d] = cell;
+    a.slotv[d] = base + (lane - hl);
   }
 }
 
@@ -150,22 +152,29 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(int32_t *bsum, int64_
 }
 
 // ---------------------------------------------------------------- stable placement + gather
-// Cell start = tile-local prefix + scanned tile total: thread t < ncell writes start[t]; thread
-// i < N places molecule i at its provisional slot of its cell (both read only lstart and bsum).
-__global__ __launch_bounds__(256) void k_scatter(const int32_t *cell_of, const int32_t *slot, const int32_t *lstart,
-                                                 const int32_t *bsum, int64_t N, int64_t ncell, int32_t *start,
-                                                 int32_t *tmp) {
+// Cell start = tile-local prefix + scanned tile total: thread t < ncell writes start[t]; visiting
+// position t < N places its molecule at its provisional slot of its cell (both read only lstart
+// and bsum).
+__global__ __launch_bounds__(256) void k_scatter(const int32_t *cellv, const int32_t *slotv, const int32_t *order,
+                                                 const int32_t *lstart, const int32_t *bsum, int64_t N, int64_t ncell,
+                                                 int32_t *start, int32_t *tmp) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < ncell) start[t] = lstart[t] + bsum[t / SCAN_TILE];
   if (t < N) {
-    const int c = cell_of[t];
-    tmp[lstart[c] + bsum[c / SCAN_TILE] + slot[t]] = (int32_t)t;
+    const int c = cellv[t];
+    tmp[lstart[c] + bsum[c / SCAN_TILE] + slotv[t]] = order ? order[t] : (int32_t)t;
   }
+}
+
+// The caller-order cell ids of the view: cell_of[order[d]] = cellv[d].
+__global__ void k_cell_of(const int32_t *cellv, const int32_t *order, int64_t N, int32_t *cell_of) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d < N) cell_of[order ? order[d] : d] = cellv[d];
 }
 
 struct GatherArgs {
   const double *pos, *quat;
-  const int32_t *comp, *cell_of, *start, *tmp, *order;
+  const int32_t *comp, *cellv, *start, *tmp, *order;
   int64_t N;
   double Lx, Ly, Lz;
   const ModelDev *md;
@@ -185,13 +194,14 @@ __device__ __forceinline__ void rotate(const double q[4], const double v[3], dou
 // smaller original index (a stable counting sort whatever order the atomic slots came in); then
 // gather the sorted copies.  The cell's entries are contiguous in tmp, so the ranking reads
 // cached words only.  Thread d takes molecule order[d] (identity without an order): in the
-// previous build's order the sorted copies are written nearly in sequence, and the COMs read are
-// the lines k_bin has just read in the same order.
+// previous build's order the sorted copies are written nearly in sequence.  The blocks of each
+// XCD (block b runs on XCD b % 8) take one contiguous eighth of that order, so the COM lines a
+// region of space gathers meet in one L2 instead of being fetched by several.
 __global__ __launch_bounds__(256) void k_rank_gather(GatherArgs a) {
-  const int64_t dd = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t dd = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (dd >= a.N) return;
   const int64_t i = a.order ? (int64_t)a.order[dd] : dd;
-  const int c = a.cell_of[i];
+  const int c = a.cellv[dd];
   const int s = a.start[c], n = a.start[c + 1] - s;
   int rank = 0;
   for (int k = 0; k < n; ++k) rank += a.tmp[s + k] < (int32_t)i ? 1 : 0;
@@ -264,6 +274,11 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 
+int launch_cell_of(const md_cells *c, hipStream_t s) {
+  k_cell_of<<<nblk(c->N, 256), 256, 0, s>>>(c->cellv, c->order, c->N, c->cell_of);
+  return check_hip(hipGetLastError(), "k_cell_of");
+}
+
 int launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
   if (n <= 0) return MD_OK;
   k_fill_i32<<<nblk(n, 256), 256, 0, s>>>(p, n, v);
@@ -289,25 +304,25 @@ int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat
   // (whole allocation, so a later build with more cells also starts from zero)
   if (!c->counts_zero && (rc = launch_fill_i32(c->count, c->cap_cell, 0, s))) return rc;
   c->counts_zero = false;
-  BinArgs b{pos,      quat,      comp,      order,     N,        c->box[0],       c->box[1],
+  BinArgs b{pos,      quat,      comp,      order,    N,        c->box[0],       c->box[1],
             c->box[2], inv_h[0], inv_h[1], inv_h[2], c->nc[0],        c->nc[1],
-            c->nc[2], m->host.ncomp, (int32_t)((m->flags & MD_CHECK) != 0), c->cell_of, c->slot, c->count,
+            c->nc[2], m->host.ncomp, (int32_t)((m->flags & MD_CHECK) != 0), c->cellv, c->slot, c->count,
             m->status};
-  k_bin<<<nblk(N, 256), 256, 0, s>>>(b);
+  k_bin<<<(unsigned)pair_blocks(nblk(N, 256)), 256, 0, s>>>(b);
   if ((rc = check_hip(hipGetLastError(), "k_bin"))) return rc;
   const int64_t nb = (c->ncell + SCAN_TILE - 1) / SCAN_TILE;
   k_scan_local<<<(unsigned)nb, SCAN_THREADS, 0, s>>>(c->count, c->ncell, c->lstart, c->bsum);
   k_scan_top<<<1, SCAN_THREADS, 0, s>>>(c->bsum, nb, c->start, c->ncell);
   if ((rc = check_hip(hipGetLastError(), "k_scan"))) return rc;
   c->counts_zero = true;
-  k_scatter<<<nblk(std::max<int64_t>(N, c->ncell), 256), 256, 0, s>>>(c->cell_of, c->slot, c->lstart, c->bsum, N,
-                                                                      c->ncell, c->start, c->tmp);
+  k_scatter<<<nblk(std::max<int64_t>(N, c->ncell), 256), 256, 0, s>>>(c->cellv, c->slot, order, c->lstart, c->bsum,
+                                                                      N, c->ncell, c->start, c->tmp);
   if ((rc = check_hip(hipGetLastError(), "k_scatter"))) return rc;
-  GatherArgs g{pos, m->single_site ? nullptr : quat, comp, c->cell_of, c->start, c->tmp, order, N,
+  GatherArgs g{pos, m->single_site ? nullptr : quat, comp, c->cellv, c->start, c->tmp, order, N,
                c->box[0], c->box[1], c->box[2], m->dev, m->shape.lj, m->shape.chg, m->shape.dip, m->shape.quad,
                c->nvec, c->perm, m->single_site ? nullptr : c->scomp, c->sx, c->sy, c->sz,
                m->single_site ? nullptr : c->svec, m->single_site ? nullptr : c->squat};
-  k_rank_gather<<<nblk(N, 256), 256, 0, s>>>(g);
+  k_rank_gather<<<(unsigned)pair_blocks(nblk(N, 256)), 256, 0, s>>>(g);
   return check_hip(hipGetLastError(), "k_rank_gather");
 }
 

@@ -107,6 +107,12 @@ struct md_cells {
   bool built = false;
   const md_model *model = nullptr;
   int32_t *cell_of = nullptr, *slot = nullptr, *tmp = nullptr, *perm = nullptr, *scomp = nullptr;
+  // cell id at each position of the last build's visiting order (slot: provisional slot, same
+  // order), and that order (NULL: index order; else perm_prev); cell_of (caller order, for
+  // md_cells_view) is formed from them on demand
+  int32_t *cellv = nullptr;
+  const int32_t *order = nullptr;
+  bool cell_of_valid = false;
   int32_t *perm_prev = nullptr;  // the other buffer of the permutation pair (previous build's order)
   int32_t *count = nullptr, *start = nullptr, *bsum = nullptr;
   int32_t *lstart = nullptr;     // tile-local exclusive prefix of the counts
@@ -193,6 +199,7 @@ int launch_adjoint(md_model *m, const md_cells *c, int precision, const AdjOut &
 // device address of the static scratch array of md_forces_noalloc on the current device (looked
 // up once per device with hipGetSymbolAddress; md_pair.hip)
 int noalloc_scratch(void **ptr);
+int launch_cell_of(const md_cells *c, hipStream_t s);  // cell_of[order[d]] = cellv[d]
 int launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 int launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 int launch_scale_copy(const double *src, double *dst, int64_t n, double a, hipStream_t s);
