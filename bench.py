@@ -76,27 +76,25 @@ def pair_flops(model):
     return f
 
 
-def pair_counters(kernel_sources):
-    """(HBM bytes, executed FP operations) per pair-kernel launch from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source (hash recorded in the summary);
-    else (None, None)."""
+def pair_counters(kernel_sources, name="k_pair_lj_c2_lj_1m_counters.md"):
+    """Per pair-kernel launch, from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source (hash recorded in the summary): HBM bytes and executed FP32 / FP64
+    operations (64 lanes x (add + mul + 2 fma + trans) per VALU instruction counted); else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_pair_lj_c2_lj_1m_counters.md")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
-        return None, None
+        return None
     h = hashlib.sha256()
     for f in kernel_sources:
         h.update(open(os.path.join(ROOT, "paper_1408_4599_amd", "csrc", f), "rb").read())
-    text = open(path).read()
-    src, val, flop = None, None, None
-    for line in text.splitlines():
-        if line.startswith("source_sha256:"):
-            src = line.split(":", 1)[1].strip()
-        if line.startswith("traffic_bytes_per_launch:"):
-            val = float(line.split(":", 1)[1].strip())
-        if line.startswith("Executed floating-point operations per dispatch"):
-            flop = float(line.rsplit(":", 1)[1].strip())
-    return (val, flop) if src == h.hexdigest() else (None, None)
+    out, src = {}, None
+    for line in open(path).read().splitlines():
+        key, _, val = line.partition(":")
+        if key == "source_sha256":
+            src = val.strip()
+        elif key in ("traffic_bytes_per_launch", "executed_fp32_flop_per_launch", "executed_fp64_flop_per_launch"):
+            out[key] = float(val.strip())
+    return out if src == h.hexdigest() else None
 
 
 def measure_extra(md, W, torch, name, evals, steps, adjoint=False, half_shell=False):
@@ -167,6 +165,39 @@ def measure_extra(md, W, torch, name, evals, steps, adjoint=False, half_shell=Fa
     return out
 
 
+def build_sweep(md, W, torch, nbuild=10):
+    """Cell build (wrap, bin, stable counting sort, sorted gather) of homogeneous LJ fluids from 2^14
+    to 2^26 molecules: rebuilds of the same configuration (as in md_step), timed with HIP events;
+    algorithmic bytes 56 per molecule + 4 per cell (single-site)."""
+    model = md.Model(W.lj_model(2.5))
+    rows = []
+    for n in (16, 32, 64, 128, 256):
+        pos, box = W.fcc_positions_device(n, 0.75, 14084599 + n, "cuda")
+        N = pos.shape[0]
+        cells = md.Cells()
+        for _ in range(2):
+            md.build_cells(model, cells, pos, None, None, box)
+        torch.cuda.synchronize()
+        model.profile(True)
+        for _ in range(nbuild):
+            md.build_cells(model, cells, pos, None, None, box)
+        ms, k = model.profile_read("build")
+        model.profile(False)
+        v = cells.view()
+        ncell = int(np.prod(v["nc"]))
+        s = ms / k / 1e3
+        byts = 56.0 * N + 4.0 * (ncell + 1)
+        rows.append({"N": N, "log2N": round(math.log2(N), 3), "cells": ncell, "ms_per_build": 1e3 * s,
+                     "algorithmic_bytes": byts, "GB_per_s": byts / s / 1e9, "frac_of_hbm_peak": byts / s / PEAK_HBM})
+        print(f"[bench] build N={N}: {1e3 * s:.4f} ms, {byts / s / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
+        cells.close()
+        del pos
+        torch.cuda.empty_cache()
+    print(json.dumps({"build_sweep": rows, "peak_hbm_GB_per_s": PEAK_HBM / 1e9,
+                      "accounting": "56 B per molecule (COM read 24, cell id 4, permutation 4, sorted COM "
+                                    "24) + 4 B per cell (start table)"}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +212,9 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run 3 plain device copies of this many MiB (HBM byte-counter calibration)")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--build-sweep", action="store_true",
+                    help="only time the cell build of homogeneous LJ fluids (rho = 0.75, r_c = 2.5) for "
+                         "N = 2^14, 2^17, 2^20, 2^23, 2^26 and print one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
@@ -195,6 +229,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.build_sweep:
+        build_sweep(md, W, torch)
+        return
     t0 = time.time()
     cfg = W.make(args.workload)
     gen_s = time.time() - t0
@@ -328,7 +365,10 @@ def main():
     value = P * args.steps / t32
     E = e32[:, 0] + e32[:, 1] + e32[:, 2]
     W_alg = DIST_TEST_FLOP * D + pair_flops(cfg["model"]) * P
-    traffic, executed = pair_counters(["md_pair.hip", "md_device.h", "md_internal.h"])
+    counters = pair_counters(["md_pair.hip", "md_device.h", "md_internal.h"]) if model.single_site else None
+    traffic = counters.get("traffic_bytes_per_launch") if counters else None
+    ex32 = counters.get("executed_fp32_flop_per_launch") if counters else None
+    ex64 = counters.get("executed_fp64_flop_per_launch") if counters else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -362,8 +402,12 @@ def main():
                      "accounting": f"{DIST_TEST_FLOP} FLOP per half-shell distance test (D) + "
                                    f"{pair_flops(cfg['model'])} FLOP per unique interacting pair (P)",
                      "frac_of_nonpacked_fp32_issue": W_alg / f32_pair / (PEAK_FP32 / 2),
-                     "executed_flop_per_launch": executed,
-                     "executed_frac": None if executed is None else executed / f32_pair / PEAK_FP32},
+                     # executed operations from the committed counter summary (None once the kernel
+                     # source has changed since it was taken), each precision against its own peak
+                     "executed_fp32_flop_per_launch": ex32,
+                     "executed_fp32_frac": None if ex32 is None else ex32 / f32_pair / PEAK_FP32,
+                     "executed_fp64_flop_per_launch": ex64,
+                     "executed_fp64_frac": None if ex64 is None else ex64 / f32_pair / PEAK_FP64},
         "cell_sort_roofline": {"bound": "hbm", "achieved": build_bytes / build_s / 1e9, "peak": PEAK_HBM / 1e9,
                                "unit": "GB/s", "frac": build_bytes / build_s / PEAK_HBM,
                                "ms_per_build": 1e3 * build_s, "algorithmic_bytes_per_build": build_bytes,
@@ -426,6 +470,30 @@ def main():
                                "sample": f"{len(idx)} of {N} molecules: full O(N) rows of the FP64 brute-force "
                                          f"oracle in {tcpu:.1f}s; rate scaled to all N rows (each pair visited "
                                          f"from both ends)"}
+        # the oracle timing protocol on these cores: the small LJTS fluid (N = 4000) evaluated in full
+        # and integrated for 100 steps; the full-size evaluations as recorded with the stored values
+        c1 = W.make("c1_ljts_4000")
+        t = time.perf_counter()
+        r1 = O.forces(c1["model"], c1["pos"], c1["quat"], c1["comp"], c1["box"])
+        t_c1 = time.perf_counter() - t
+        t = time.perf_counter()
+        O.step(c1["model"], c1["pos"], c1["vel"], c1["quat"], c1["angmom"], c1["comp"], c1["box"], c1["dt"], 100)
+        t_c1s = time.perf_counter() - t
+        n1 = c1["pos"].shape[0]
+        golden_path = os.path.join(ROOT, "tests", "golden", "full_size.json")
+        full = json.load(open(golden_path)) if os.path.exists(golden_path) else {}
+        out["oracle_protocol"] = {
+            "cores": O.num_threads(), "cpu_model": cpu_model,
+            "c1_ljts_4000": {"full_evaluation_s": t_c1, "pair_tests_per_s": n1 * (n1 - 1) / 2 / t_c1,
+                             "interactions_per_s": r1["npairs"] / t_c1, "steps": 100, "steps_s": t_c1s,
+                             "steps_per_s": 100 / t_c1s},
+            "full_size_evaluations": {k: {"seconds": v["oracle_seconds"], "threads": v["threads"],
+                                          "interactions_per_s": v["npairs"] / v["oracle_seconds"],
+                                          "pair_tests_per_s": v["N"] * (v["N"] - 1) / 2 / v["oracle_seconds"]}
+                                      for k, v in full.items()},
+            "note": "full-size evaluations: the brute-force oracle over all N^2 pairs, timed when the stored "
+                    "energies were written (tests/golden/make_full_size.py, in the build container, threads "
+                    "as stated); the C1 figures are measured here, on the cores above"}
     print(json.dumps(out), flush=True)
 
 

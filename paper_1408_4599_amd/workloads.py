@@ -133,6 +133,25 @@ def fcc_lattice(n: int, a: float) -> np.ndarray:
     return (pts + 0.25) * a
 
 
+def fcc_positions_device(n: int, rho: float, seed: int, device, amp=0.05):
+    """Large inputs made on a torch device: the n^3 FCC cells of fcc_lattice (same site order) at
+    density rho with uniform jitter in [-amp, amp) from a seeded torch generator.  Returns
+    (pos [4 n^3, 3] float64 tensor, box)."""
+    import torch
+    N = 4 * n ** 3
+    L = (N / rho) ** (1.0 / 3.0)
+    a = L / n
+    idx = torch.arange(n ** 3, device=device, dtype=torch.int64)
+    ijk = torch.stack((idx // (n * n), (idx // n) % n, idx % n), dim=1).to(torch.float64)
+    basis = torch.tensor([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]], device=device, dtype=torch.float64)
+    pos = ((ijk[:, None, :] + basis[None, :, :]).reshape(-1, 3) + 0.25) * a
+    del ijk, idx
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    pos += (torch.rand(pos.shape, generator=g, device=device, dtype=torch.float64) * 2.0 - 1.0) * amp
+    return pos, [L, L, L]
+
+
 def jitter(rng, pos, amp=0.05):
     return pos + rng.uniform(-amp, amp, size=pos.shape)
 
