@@ -208,6 +208,7 @@ __device__ __forceinline__ void write_partial_block(double *partial, double acc5
 constexpr int QCELLS = 48;  // 3 x 4 x 4 staged cells
 constexpr int NSMAX = 8;
 constexpr int SLACK = 32;  // spare tile entries read (never counted) past the end of a walk
+constexpr unsigned short LIST_END = 0xFFFF;  // end marker of a hit list (slots stay below 4096)
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 // LJ constants of the single-site kernels: FP64 model values, their FP32 roundings for the FP32
@@ -439,61 +440,66 @@ __global__ __launch_bounds__(256) void k_pair_lj(CellsDev c, LJK k, PairOut o, i
               }
               wave_sync_lds();
             }
-            // two candidates per iteration, both loaded before either is tested.  Only the last
-            // iteration can pass the end of the range (its extra slots are read, never counted),
-            // and only the home layer holds the molecule itself.
-            // slice s tests the adjacent slots 2 s, 2 s + 1 of every run of 2 NS candidates; the
-            // pair of the next run is loaded before the current one is tested (the walk reads up
-            // to 4 NS - 1 slots past the range: the tile keeps SLACK spare entries)
-            auto walk = [&](auto tail, auto home) {
-              int sa = cs + 2 * sla - off;  // slot of this lane's first candidate
-              const int send = ce - off, sself = self - off;
-              using V = typename std::conditional<F32, f4v, double>::type;
+            // candidate pair (slots t, t + 1): FP32 test operands, or FP64 positions
+            using V = typename std::conditional<F32, f4v, double>::type;
+            struct Cand {
               V a0, a1, a2, b0, b1, b2;
-              auto load = [&](int t) {
-                if constexpr (F32) {
-                  a0 = l32[t], b0 = l32[t + 1];
-                } else {
-                  a0 = l64[3 * t], a1 = l64[3 * t + 1], a2 = l64[3 * t + 2];
-                  b0 = l64[3 * t + 3], b1 = l64[3 * t + 4], b2 = l64[3 * t + 5];
-                }
-              };
-              load(sa);
-              for (int kb = cs; tail ? kb < ce : kb + 2 * NS <= ce; kb += 2 * NS, sa += 2 * NS) {
-                bool ha, hb;
-                if constexpr (F32) {
-                  const f4v qa = a0, qb = b0;
-                  if (!tail) load(sa + 2 * NS);
-                  ha = fmaf(az, qa.z, fmaf(ay, qa.y, fmaf(ax, qa.x, qa.w))) < thri;
-                  hb = fmaf(az, qb.z, fmaf(ay, qb.y, fmaf(ax, qb.x, qb.w))) < thri;
-                } else {
-                  const double pax = xi - a0, pay = yi - a1, paz = zi - a2;
-                  const double pbx = xi - b0, pby = yi - b1, pbz = zi - b2;
-                  if (!tail) load(sa + 2 * NS);
-                  ha = fma(paz, paz, fma(pay, pay, pax * pax)) < rc2;
-                  hb = fma(pbz, pbz, fma(pby, pby, pbx * pbx)) < rc2;
-                }
-                if (tail) ha = ha && sa < send, hb = hb && sa + 1 < send;
-                if (home) ha = ha && sa != sself, hb = hb && sa + 1 != sself;
-                // the slot is always written; the count advances on a hit
-                *lp = (unsigned short)sa;
-                lp += ha ? 64 : 0;
-                *lp = (unsigned short)(sa + 1);
-                lp += hb ? 64 : 0;
-                if (__any(lp > lplim)) flush();
-                if (tail) break;
+            };
+            auto load = [&](Cand &q, int t) {
+              if constexpr (F32) {
+                q.a0 = l32[t], q.b0 = l32[t + 1];
+              } else {
+                q.a0 = l64[3 * t], q.a1 = l64[3 * t + 1], q.a2 = l64[3 * t + 2];
+                q.b0 = l64[3 * t + 3], q.b1 = l64[3 * t + 4], q.b2 = l64[3 * t + 5];
               }
             };
-            const int cfull = cs + div_small(ce - cs, r2ns) * (2 * NS);
-            if (d == 1) walk(std::false_type(), std::true_type());
-            else walk(std::false_type(), std::false_type());
-            if (cfull < ce) {
-              const int cs0 = cs;
-              cs = cfull;
-              if (d == 1) walk(std::true_type(), std::true_type());
-              else walk(std::true_type(), std::false_type());
-              cs = cs0;
-            }
+            // test the pair at slot t, list the hits (the slot is always written; the count
+            // advances on a hit); lim: slots at or past it are not candidates (tail only)
+            auto step = [&](const Cand &q, int t, int sself, int lim, auto tail, auto home) {
+              bool ha, hb;
+              if constexpr (F32) {
+                ha = fmaf(az, q.a0.z, fmaf(ay, q.a0.y, fmaf(ax, q.a0.x, q.a0.w))) < thri;
+                hb = fmaf(az, q.b0.z, fmaf(ay, q.b0.y, fmaf(ax, q.b0.x, q.b0.w))) < thri;
+              } else {
+                const double pax = xi - q.a0, pay = yi - q.a1, paz = zi - q.a2;
+                const double pbx = xi - q.b0, pby = yi - q.b1, pbz = zi - q.b2;
+                ha = fma(paz, paz, fma(pay, pay, pax * pax)) < rc2;
+                hb = fma(pbz, pbz, fma(pby, pby, pbx * pbx)) < rc2;
+              }
+              if (tail) ha = ha && t < lim, hb = hb && t + 1 < lim;
+              if (home) ha = ha && t != sself, hb = hb && t + 1 != sself;
+              *lp = (unsigned short)t;
+              lp += ha ? 64 : 0;
+              *lp = (unsigned short)(t + 1);
+              lp += hb ? 64 : 0;
+              if (__any(lp > lplim)) flush();
+            };
+            // slice s tests the adjacent slots 2 s, 2 s + 1 of every run of 2 NS candidates, two
+            // runs per trip with the next run's pair loaded before the current one is tested.
+            // The walk reads up to 2 NS - 1 slots past the range (the tile keeps SLACK spare
+            // entries); only the last, partial run is bounds-checked, and only the home layer
+            // holds the molecule itself.
+            auto walk = [&](auto home) {
+              int sa = cs + 2 * sla - off;  // slot of this lane's first candidate
+              const int send = ce - off, sself = self - off;
+              Cand A, B;
+              load(A, sa);
+              int kb = cs;
+              for (; kb + 4 * NS <= ce; kb += 4 * NS, sa += 4 * NS) {
+                load(B, sa + 2 * NS);
+                step(A, sa, sself, send, std::false_type(), home);
+                load(A, sa + 4 * NS);
+                step(B, sa + 2 * NS, sself, send, std::false_type(), home);
+              }
+              if (kb + 2 * NS <= ce) {
+                step(A, sa, sself, send, std::false_type(), home);
+                kb += 2 * NS, sa += 2 * NS;
+                if (kb < ce) load(A, sa);
+              }
+              if (kb < ce) step(A, sa, sself, send, std::true_type(), home);
+            };
+            if (d == 1) walk(std::true_type());
+            else walk(std::false_type());
           }
         }
         flush();
