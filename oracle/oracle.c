@@ -146,6 +146,29 @@ int64_t oracle_bin(const double *pos, int64_t N, const double *box, double rc, i
   return (int64_t)nc[0] * nc[1] * nc[2];
 }
 
+/* Half-edge cells (Sec. 3, the r_c/2 variant of the linked cells): the grid of 2 n_k cells of
+ * edge L_k / (2 n_k) per axis, after the same wrap as oracle_bin.  half_of[3 i + k] =
+ * min(2 n_k - 1, floor(xw_k * (2 n_k / L_k))).  Each edge-r_c cell of oracle_bin is made of the
+ * 2 x 2 x 2 half-edge cells whose indices halved (integer division) are its cell coordinates.
+ * Returns 8 x the number of edge-r_c cells, or -1 if the box is too small for three cells per
+ * axis.                                                                                          */
+int64_t oracle_half_cells(const double *pos, int64_t N, const double *box, double rc, int32_t *half_of) {
+  int32_t nc[3];
+  if (!oracle_ncells(box, rc, nc)) return -1;
+  double inv_hh[3];
+  for (int k = 0; k < 3; ++k) inv_hh[k] = (double)(2 * nc[k]) / box[k];
+  for (int64_t i = 0; i < N; ++i) {
+    for (int k = 0; k < 3; ++k) {
+      const double xw = om_wrap(pos[3 * i + k], box[k]);
+      int32_t s = (int32_t)floor(xw * inv_hh[k]);
+      if (s > 2 * nc[k] - 1) s = 2 * nc[k] - 1;
+      if (s < 0) s = 0;
+      half_of[3 * i + k] = s;
+    }
+  }
+  return 8 * (int64_t)nc[0] * nc[1] * nc[2];
+}
+
 /* ---------------------------------------------------------------- one site pair */
 
 /* Energy and partial derivatives of one electrostatic site pair, as a function of the distance r

@@ -63,6 +63,8 @@ def lib():
         L.oracle_ncells.restype = ctypes.c_int
         L.oracle_bin.argtypes = [dp, ctypes.c_int64, dp, ctypes.c_double, ip, dp]
         L.oracle_bin.restype = ctypes.c_int64
+        L.oracle_half_cells.argtypes = [dp, ctypes.c_int64, dp, ctypes.c_double, ip]
+        L.oracle_half_cells.restype = ctypes.c_int64
         L.oracle_rows.argtypes = [mp, dp, dp, ip, ctypes.c_int64, dp, lp, ctypes.c_int64,
                                   dp, dp, dp, dp, dp, lp, dp]
         L.oracle_rows.restype = ctypes.c_int
@@ -151,6 +153,29 @@ def bin_cells(pos, box, rc):
     if n < 0:
         raise ValueError("box smaller than three cells per axis")
     return cell_of, pw, int(n)
+
+
+def half_cells(pos, box, rc):
+    """Half-edge (r_c/2) cell coordinates of every molecule: int32[N, 3] (x, y, z), after the wrap
+    of ``bin_cells``."""
+    pos = _f64(pos, (-1, 3))
+    N = pos.shape[0]
+    half = np.zeros((N, 3), dtype=np.int32)
+    n = lib().oracle_half_cells(_dp(pos), N, _dp(_f64(box, 3)), float(rc), _ip(half))
+    if n < 0:
+        raise ValueError("box smaller than three cells per axis")
+    return half
+
+
+def subcell_order(pos, box, rc):
+    """The stable order of molecules by r_c cell, then by half-edge cell inside it (octant
+    4 z + 2 y + x of the half indices' low bits), then by original index; also each molecule's
+    key 8 * cell + octant."""
+    cell_of, _, _ = bin_cells(pos, box, rc)
+    half = half_cells(pos, box, rc).astype(np.int64)
+    octant = 4 * (half[:, 2] & 1) + 2 * (half[:, 1] & 1) + (half[:, 0] & 1)
+    key = 8 * cell_of.astype(np.int64) + octant
+    return np.lexsort((np.arange(len(key)), key)), key
 
 
 def _system(model, pos, quat, comp):

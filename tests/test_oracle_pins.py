@@ -345,6 +345,64 @@ def test_cells_per_axis_rule(oracle):
     assert oracle.ncells([7.4, 10.0, 10.0], 2.5) is None
 
 
+def test_half_cells_refine_cells(oracle):
+    """Half-edge cells (Sec. 3, r_c/2 variant): every molecule's half-cell coordinates halved are
+    its cell coordinates, and its wrapped coordinate lies in the half-cell's slab (to one rounding
+    at faces); hand-worked values on a box of 3 cells of edge 10/3 per axis."""
+    cfg = W.random_gas(5000, [9.1, 11.7, 14.2], W.lj_model(2.5), seed=18)
+    box = np.asarray(cfg["box"])
+    nc = np.array(oracle.ncells(box, 2.5))
+    hh = box / (2 * nc)
+    # random positions far outside the box, plus positions on every half-cell face and at 0, L
+    faces = np.stack(np.meshgrid(*[np.arange(2 * n + 1) * h for n, h in zip(nc, hh)], indexing="ij"), -1)
+    pos = np.concatenate([cfg["pos"] * 3.0 - 10.0, faces.reshape(-1, 3), faces.reshape(-1, 3) * (1 - 2 ** -52),
+                          -faces.reshape(-1, 3)])
+    cell, pw, _ = oracle.bin_cells(pos, box, 2.5)
+    half = oracle.half_cells(pos, box, 2.5)
+    coords = np.stack([cell % nc[0], (cell // nc[0]) % nc[1], cell // (nc[0] * nc[1])], -1)
+    np.testing.assert_array_equal(half // 2, coords)
+    assert (half >= 0).all() and (half < 2 * nc).all()
+    assert (pw >= half * hh - 1e-12).all() and (pw < (half + 1) * hh + 1e-12).all()
+    # 3 cells of edge 10/3 (edge 2.5 is refused: it must exceed r_c), half-cells of edge 5/3
+    h = oracle.half_cells([[1.7, 5.0, 9.99], [1.6, 3.4, -0.1]], [10.0, 10.0, 10.0], 2.5)
+    np.testing.assert_array_equal(h, [[1, 3, 5], [0, 2, 5]])
+
+
+@pytest.mark.parametrize("seed,rho", [(21, 0.9), (22, 0.3)])
+def test_half_cell_culling_keeps_every_pair(oracle, seed, rho):
+    """The half-edge-cell culling rule: within the 27 cells around a home cell, a partner whose
+    half-cell lies three half-cells away from the home molecule's along any axis (the far half
+    of a neighbour cell) is more than one cell edge >= r_c away along that axis, so no pair inside
+    the cutoff is ever culled.  Brute force over all pairs of dense and dilute fluids, with
+    positions snapped onto half-cell faces."""
+    rng = W.rng_for(seed)
+    N = 1500
+    box = np.array([1.0, 1.2, 1.45]) * (N / rho / 1.74) ** (1 / 3)
+    nc = np.array(oracle.ncells(box, 2.5))
+    hh = box / (2 * nc)
+    pos = rng.uniform(0, 1, size=(N, 3)) * box
+    snap = rng.uniform(size=(N, 3)) < 0.3  # a third of the coordinates exactly on a half-cell face
+    pos = np.where(snap, np.round(pos / hh) * hh, pos)
+    cell, pw, _ = oracle.bin_cells(pos, box, 2.5)
+    half = oracle.half_cells(pos, box, 2.5).astype(np.int64)
+    c = np.stack([cell % nc[0], (cell // nc[0]) % nc[1], cell // (nc[0] * nc[1])], -1).astype(np.int64)
+    d = pw[:, None, :] - pw[None, :, :]
+    d -= box * np.round(d / box)
+    r2 = (d * d).sum(-1)
+    i, j = np.nonzero((r2 < 2.5 ** 2 * (1 + 1e-9)) & ~np.eye(N, dtype=bool))
+    assert len(i) > 5 * N * rho
+    # image of j next to i: cell offset in {-1, 0, 1} per axis, half-cell offset of that image
+    dc = (c[j] - c[i] + 1) % nc - 1
+    assert (np.abs(dc) <= 1).all()
+    ds = half[j] - half[i] + 2 * (dc - (c[j] - c[i]))
+    assert (np.abs(ds) <= 2).all()
+    # and the rule does cull: some pairs three half-cells apart exist, all outside the cutoff
+    far = np.abs((half[:, None, :] - half[None, :, :] + 2 * ((c[None, :, :] - c[:, None, :] + 1) % nc - 1
+                                                             - (c[None, :, :] - c[:, None, :]))))
+    culled = (far == 3).any(-1)
+    assert culled.sum() > 0 and (r2[culled] >= 2.5 ** 2).all()
+
+
 # ----------------------------------------------------------------------------- integrator
 
 def _energy_spread(en):
