@@ -48,6 +48,32 @@ def distance_tests(counts3d):
     return float(nd.sum() - 0.5 * c.sum())
 
 
+def walk_tests(view):
+    """Distance tests of the single-site cutoff walk per evaluation, counted from the cell
+    occupancy: every molecule against every molecule of its 27 cells (itself included), and with
+    half-edge cells (sub_start present) against the five z half-layers around its own z-half in
+    each of its nine cell columns (Sec. 3, cells of edge r_c/2)."""
+    nx, ny, nz = view["nc"]
+    cells = np.diff(view["cell_start"].cpu().numpy().astype(np.int64)).reshape(nz, ny, nx)
+    nb = np.zeros_like(cells)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                nb += np.roll(cells, (dz, dy, dx), axis=(0, 1, 2))
+    out = {"full_27_cells": float((cells * nb).sum())}
+    if view.get("sub_start") is not None:
+        octs = np.diff(view["sub_start"].cpu().numpy().astype(np.int64)).reshape(nz, ny, nx, 8)
+        half = np.stack([octs[..., 0:4].sum(-1), octs[..., 4:8].sum(-1)], axis=1).reshape(2 * nz, ny, nx)
+        col = np.zeros_like(half)
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                col += np.roll(half, (dy, dx), axis=(1, 2))
+        win = sum(np.roll(col, -k, axis=0) for k in range(-2, 3))
+        out["half_edge_z_culled"] = float((half * win).sum())
+        out["ratio"] = out["half_edge_z_culled"] / out["full_27_cells"]
+    return out
+
+
 # Algorithmic FLOP per unordered molecule pair inside the cutoff, counted from the interaction
 # formulas as written (Sec. 2 models; FMA = 2, reciprocal / reciprocal square root = 1,
 # compare = 0; each pair once).  Site pair terms include the site separation (6), r^2 (5), the
@@ -97,13 +123,14 @@ def pair_counters(kernel_sources, name="k_pair_lj_c2_lj_1m_counters.md"):
     return out if src == h.hexdigest() else None
 
 
-def measure_extra(md, W, torch, name, evals, steps, adjoint=False, half_shell=False):
+def measure_extra(md, W, torch, name, evals, steps, adjoint=False, half_shell=False, subcells=False):
     """Forces-only and md_step throughput of one more workload (FP32 and FP64); half_shell selects
-    the half-shell pair kernel for a single-site model (MD_HALF_SHELL)."""
+    the half-shell pair kernel for a single-site model (MD_HALF_SHELL), subcells the half-edge
+    cell order and walk (MD_SUBCELLS)."""
     cfg = W.make(name)
     N = cfg["pos"].shape[0]
     dev = lambda a, dt=torch.float64: None if a is None else torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
-    model = md.Model(cfg["model"], half_shell=half_shell)
+    model = md.Model(cfg["model"], half_shell=half_shell, subcells=subcells)
     cells = md.Cells()
     multi = cfg["quat"] is not None
     md.build_cells(model, cells, dev(cfg["pos"]), dev(cfg["quat"]), None, cfg["box"])
@@ -117,6 +144,9 @@ def measure_extra(md, W, torch, name, evals, steps, adjoint=False, half_shell=Fa
     W_alg = DIST_TEST_FLOP * D + pair_flops(cfg["model"]) * P
     out["algorithmic_flop_per_evaluation"] = W_alg
     out["flop_per_pair"] = pair_flops(cfg["model"])
+    if model.single_site and not half_shell:
+        out["walk_distance_tests"] = walk_tests(v)
+        out["half_edge_cells"] = subcells
     for prec in ("fp32", "fp64"):
         buf = {"force": torch.empty((N, 3), dtype=torch.float64, device="cuda"),
                "uw": torch.empty(5, dtype=torch.float64, device="cuda"),
@@ -165,11 +195,17 @@ def measure_extra(md, W, torch, name, evals, steps, adjoint=False, half_shell=Fa
     return out
 
 
-def build_sweep(md, W, torch, nbuild=10):
+def start_table_bytes(ncell, subcells):
+    """Bytes of the start tables a build writes: one int32 per bin plus the total, and with
+    half-edge cells (8 bins per cell) also the cell starts."""
+    return 4.0 * (8 * ncell + 1) + 4.0 * (ncell + 1) if subcells else 4.0 * (ncell + 1)
+
+
+def build_sweep(md, W, torch, nbuild=10, subcells=True):
     """Cell build (wrap, bin, stable counting sort, sorted gather) of homogeneous LJ fluids from 2^14
     to 2^26 molecules: rebuilds of the same configuration (as in md_step), timed with HIP events;
-    algorithmic bytes 56 per molecule + 4 per cell (single-site)."""
-    model = md.Model(W.lj_model(2.5))
+    algorithmic bytes 56 per molecule + the start tables (single-site)."""
+    model = md.Model(W.lj_model(2.5), subcells=subcells)
     rows = []
     for n in (16, 32, 64, 128, 256):
         pos, box = W.fcc_positions_device(n, 0.75, 14084599 + n, "cuda")
@@ -186,16 +222,17 @@ def build_sweep(md, W, torch, nbuild=10):
         v = cells.view()
         ncell = int(np.prod(v["nc"]))
         s = ms / k / 1e3
-        byts = 56.0 * N + 4.0 * (ncell + 1)
+        byts = 56.0 * N + start_table_bytes(ncell, subcells)
         rows.append({"N": N, "log2N": round(math.log2(N), 3), "cells": ncell, "ms_per_build": 1e3 * s,
                      "algorithmic_bytes": byts, "GB_per_s": byts / s / 1e9, "frac_of_hbm_peak": byts / s / PEAK_HBM})
         print(f"[bench] build N={N}: {1e3 * s:.4f} ms, {byts / s / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
         cells.close()
         del pos
         torch.cuda.empty_cache()
-    print(json.dumps({"build_sweep": rows, "peak_hbm_GB_per_s": PEAK_HBM / 1e9,
+    print(json.dumps({"build_sweep": rows, "peak_hbm_GB_per_s": PEAK_HBM / 1e9, "half_edge_cells": subcells,
                       "accounting": "56 B per molecule (COM read 24, cell id 4, permutation 4, sorted COM "
-                                    "24) + 4 B per cell (start table)"}), flush=True)
+                                    "24) + 4 B per start-table entry (8 half-cells + 1 cell entry per cell "
+                                    "with half-edge cells)"}), flush=True)
 
 
 def main():
@@ -212,6 +249,8 @@ def main():
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run 3 plain device copies of this many MiB (HBM byte-counter calibration)")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--no-subcells", action="store_true",
+                    help="single-site models: plain cell order and 27-cell walk instead of half-edge cells")
     ap.add_argument("--build-sweep", action="store_true",
                     help="only time the cell build of homogeneous LJ fluids (rho = 0.75, r_c = 2.5) for "
                          "N = 2^14, 2^17, 2^20, 2^23, 2^26 and print one JSON line")
@@ -230,7 +269,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.build_sweep:
-        build_sweep(md, W, torch)
+        build_sweep(md, W, torch, subcells=not args.no_subcells)
         return
     t0 = time.time()
     cfg = W.make(args.workload)
@@ -240,7 +279,9 @@ def main():
     multi = cfg["quat"] is not None
     ncomp = len(cfg["model"]["components"])
     comp_t = dev(cfg["comp"], torch.int32) if ncomp > 1 else None
-    model = md.Model(cfg["model"])
+    single = cfg["quat"] is None and ncomp == 1
+    subcells = single and not args.no_subcells
+    model = md.Model(cfg["model"], subcells=subcells)
     cells = md.Cells()
     print(f"[bench] workload {args.workload}: N={N}, box={cfg['box'].tolist()}, generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
@@ -320,7 +361,7 @@ def main():
         nv = sum(max(k.count(kind) for k in kinds) * w for kind, w in
                  (("lj", 1), ("charge", 1), ("dipole", 2), ("quadrupole", 2)))
         build_bytes_mol += 40.0 + 24.0 * nv
-    build_bytes = build_bytes_mol * N + 4.0 * (ncell_total + 1)
+    build_bytes = build_bytes_mol * N + start_table_bytes(ncell_total, subcells)
 
     f32_wall, f32_pair = time_forces("fp32", args.force_evals)
     f64_wall, f64_pair = (None, None) if args.no_fp64 else time_forces("fp64", args.force_evals)
@@ -385,8 +426,12 @@ def main():
         "config": {"workload": args.workload, "N": N, "box": cfg["box"].tolist(), "rc": cfg["model"]["rc"],
                    "lj_shift": cfg["model"]["lj_shift"], "dt": cfg["dt"], "T": cfg["T"],
                    "cells": list(v["nc"]), "interacting_pairs": P, "distance_tests_half_shell": D,
+                   "half_edge_cells": subcells,
+                   "walk_distance_tests": walk_tests(v) if model.single_site else None,
                    "note": "interactions/s = unique COM-cutoff pairs x steps / wall time of md_step (cell rebuild, "
-                           "forces and leapfrog every step); f32 site-site arithmetic, f64 COM test and sums"},
+                           "forces and leapfrog every step); FP32 cutoff test with guard band and FP32 force "
+                           "algebra, FP64 pair decisions, energies and sums; single-site models with the "
+                           "half-edge (r_c/2) cell order and z-culled walk"},
         "steps_per_s": args.steps / t32,
         "forces_only": {"fp32_interactions_per_s": P / f32_wall, "fp32_ms": 1e3 * f32_wall,
                         "fp32_pair_kernel_ms": 1e3 * f32_pair},
@@ -397,7 +442,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": W_alg / f32_pair / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": W_alg / f32_pair / PEAK_FP32,
                      "traffic": traffic,
-                     "kernel": "k_pair_lj<float>" if model.single_site else "k_pair_ms<float>",
+                     "kernel": ("k_pair_lj<float, true>" if subcells else "k_pair_lj<float, false>")
+                               if model.single_site else "k_pair_ms<float>",
                      "algorithmic_flop_per_launch": W_alg,
                      "accounting": f"{DIST_TEST_FLOP} FLOP per half-shell distance test (D) + "
                                    f"{pair_flops(cfg['model'])} FLOP per unique interacting pair (P)",
@@ -411,7 +457,8 @@ def main():
         "cell_sort_roofline": {"bound": "hbm", "achieved": build_bytes / build_s / 1e9, "peak": PEAK_HBM / 1e9,
                                "unit": "GB/s", "frac": build_bytes / build_s / PEAK_HBM,
                                "ms_per_build": 1e3 * build_s, "algorithmic_bytes_per_build": build_bytes,
-                               "accounting": f"{build_bytes_mol:.0f} B per molecule + 4 B per cell",
+                               "accounting": f"{build_bytes_mol:.0f} B per molecule + 4 B per start-table entry "
+                                             f"({'8 half-cells + 1 cell' if subcells else '1'} per cell)",
                                "kernels": "k_bin, k_scan_local, k_scan_top, k_scatter, k_rank_gather"},
     }
     if not args.no_fp64:
@@ -434,12 +481,13 @@ def main():
 
     if not args.no_extra:
         extra = {}
-        for key, name, ev, st, adj, hs in (("c3_lj_slab_2m", "c3_lj_slab_2m", 20, 20, False, False),
-                                           ("c3_lj_slab_2m_half_shell", "c3_lj_slab_2m", 20, 20, False, True),
-                                           ("c4_2cljq_500k", "c4_2cljq_500k", 10, 10, False, False),
-                                           ("c5_4site_200k", "c5_4site_200k", 10, 10, True, False)):
+        for key, name, ev, st, adj, hs, sc in (
+                ("c3_lj_slab_2m", "c3_lj_slab_2m", 20, 20, False, False, not args.no_subcells),
+                ("c3_lj_slab_2m_half_shell", "c3_lj_slab_2m", 20, 20, False, True, False),
+                ("c4_2cljq_500k", "c4_2cljq_500k", 10, 10, False, False, False),
+                ("c5_4site_200k", "c5_4site_200k", 10, 10, True, False, False)):
             print(f"[bench] extra workload {key}", file=sys.stderr, flush=True)
-            extra[key] = measure_extra(md, W, torch, name, ev, st, adj, hs)
+            extra[key] = measure_extra(md, W, torch, name, ev, st, adj, hs, sc)
         out["workloads"] = extra
 
     # ---- oracle rows: FP32 errors on a sample and the CPU baseline ----

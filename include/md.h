@@ -61,12 +61,21 @@ enum {
                               Faster for strongly uneven cell occupancy (a vapour-liquid slab),
                               slower for homogeneous fluids; results differ from the default
                               kernel by rounding only.  No effect on multi-site models. */
+#define MD_SUBCELLS 0x8u /* single-site models without MD_HALF_SHELL: sort the molecules of each
+                            cell by half-edge (r_c/2) cell (Sec. 3) and skip, in the cutoff walk,
+                            the far z-half of the cell layer above or below a molecule's own
+                            z-half, which lies more than one cell edge (>= r_c) away.  The pair set
+                            is unchanged, the results differ by rounding only;
+                            md_cells_info.sub_start gives the half-edge cell ranges. */
 
 /* precision argument */
 #define MD_FP64 0 /* all pair arithmetic and accumulation in FP64 */
-#define MD_FP32 1 /* reciprocals seeded in FP32, single-site LJ force scalars and multipole terms
-                     in FP32; COM test, LJ site separations, multi-site LJ terms, pair energies,
-                     accumulation and reductions in FP64 */
+#define MD_FP32 1 /* single-site LJ: cutoff test in FP32 with a proven guard band, every listed
+                     pair decided exactly in FP64 (the pair set is the FP64 one), force and virial
+                     in FP32, per-molecule sums cascaded from FP32 into FP64.  Multi-site:
+                     reciprocals seeded in FP32, multipole terms in FP32; COM test, LJ site
+                     separations, LJ terms and pair energies in FP64.  Energies, accumulation
+                     across flushes and all reductions in FP64. */
 
 /* device status word bits (md_status) */
 #define MD_DEV_NONFINITE 0x1 /* a position was NaN/Inf: that molecule is spread into cell
@@ -114,7 +123,8 @@ typedef struct md_cells md_cells; /* opaque: cell grid + molecules sorted into c
  * on its first call after a build (syncs the model's last stream).  Cells have edge h_k = L_k / n_k > r_c,
  * n_k = floor(L_k / r_c) reduced until h_k >= r_c (1 + 2^-30); linear cell id
  * (c_z n_y + c_y) n_x + c_x.  Molecules are sorted stably by cell: within a cell by original
- * index. */
+ * index, or with MD_SUBCELLS by half-edge cell s_k = min(2 n_k - 1, floor(x_w * (2 n_k / L_k)))
+ * (octant 4 (s_z mod 2) + 2 (s_y mod 2) + (s_x mod 2)), then by original index. */
 typedef struct {
   int64_t N;
   int64_t ncell;
@@ -123,6 +133,9 @@ typedef struct {
   const int32_t *cell_of;    /* [N] cell of each molecule, original order */
   const int32_t *cell_start; /* [ncell + 1] first sorted slot of each cell */
   const int32_t *perm;       /* [N] original index of the molecule in each sorted slot */
+  const int32_t *sub_start;  /* [8 ncell + 1] with MD_SUBCELLS: first sorted slot of half-edge cell
+                              * 8 c + 4 z + 2 y + x (x, y, z the low bits of its half-cell
+                              * coordinates) of cell c; else NULL */
 } md_cells_info;
 
 /* Create a model from ncomp host component descriptions (Sec. 2).  xi, eta: host
@@ -131,7 +144,7 @@ typedef struct {
  * cutoff.  eps_rf: reaction-field permittivity, INFINITY allowed, applied to dipole-dipole site
  * pairs of molecule pairs inside the cutoff as -kappa mu_a.mu_b / r_c^3 with
  * kappa = 2 (eps_rf - 1) / (2 eps_rf + 1) (kappa = 1 at infinity).  flags: MD_LJ_SHIFT,
- * MD_CHECK, MD_HALF_SHELL.  *out receives the model (owned by the caller, free with md_model_destroy).
+ * MD_CHECK, MD_HALF_SHELL, MD_SUBCELLS.  *out receives the model (owned by the caller, free with md_model_destroy).
  * Allocates device memory on the current device.  Errors: MD_EINVAL, MD_ECOMP, MD_ENONFINITE,
  * MD_ENOMEM, MD_EHIP. */
 int md_model_create(const md_component_desc *comps, int32_t ncomp, const double *xi, const double *eta, double rc,

@@ -176,7 +176,8 @@ int md_model_create(const md_component_desc *comps, int32_t ncomp, const double 
   if (!std::isfinite(rc)) return set_error(MD_ENONFINITE, "md_model_create: r_c not finite");
   if (!(rc > 0.0)) return set_error(MD_EINVAL, "md_model_create: r_c <= 0");
   if (std::isnan(eps_rf) || !(eps_rf > 0.0)) return set_error(MD_EINVAL, "md_model_create: eps_rf must be > 0");
-  if (flags & ~(MD_LJ_SHIFT | MD_CHECK | MD_HALF_SHELL)) return set_error(MD_EINVAL, "md_model_create: unknown flag");
+  if (flags & ~(MD_LJ_SHIFT | MD_CHECK | MD_HALF_SHELL | MD_SUBCELLS))
+    return set_error(MD_EINVAL, "md_model_create: unknown flag");
   md_model tmp;
   ModelDev &h = tmp.host;
   std::memset(&h, 0, sizeof h);
@@ -361,7 +362,7 @@ int md_cells_destroy(md_cells *c) {
   if (!c) return MD_OK;
   dfree(c->cell_of), dfree(c->cellv), dfree(c->slot), dfree(c->tmp), dfree(c->perm), dfree(c->perm_prev);
   dfree(c->scomp);
-  dfree(c->count), dfree(c->start), dfree(c->bsum), dfree(c->lstart);
+  dfree(c->count), dfree(c->start), dfree(c->bsum), dfree(c->lstart), dfree(c->cstart);
   dfree(c->sx), dfree(c->sy), dfree(c->sz), dfree(c->svec), dfree(c->squat);
   delete c;
   return MD_OK;
@@ -382,8 +383,9 @@ int md_cells_view(const md_cells *c, md_cells_info *out) {
   out->ncell = c->ncell;
   for (int k = 0; k < 3; ++k) out->nc[k] = c->nc[k], out->box[k] = c->box[k];
   out->cell_of = c->cell_of;
-  out->cell_start = c->start;
+  out->cell_start = c->sub ? c->cstart : c->start;
   out->perm = c->perm;
+  out->sub_start = c->sub ? c->start : nullptr;
   return MD_OK;
 }
 
@@ -430,16 +432,20 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
     c->cap_nvec = nvec;
   }
   if (!m->single_site && (rc = grow(c->squat, c->cap_squat, 4 * N, "squat"))) return rc;
-  if (ncell + 1 > capC) {
+  // half-edge cells: single-site models evaluated from both ends, on request
+  const bool sub = (m->flags & MD_SUBCELLS) && m->single_site && !(m->flags & MD_HALF_SHELL);
+  const int64_t nbin = sub ? 8 * ncell : ncell;
+  if (nbin + 1 > capC) {
     int64_t cap = 0;
     c->counts_zero = false;
     c->cap_cell = 0;  // stays 0 if an allocation below fails, so the next build retries
-    if ((rc = grow(c->count, cap, ncell + 1, "count")) || (cap = 0, rc = grow(c->start, cap, ncell + 1, "start")) ||
-        (cap = 0, rc = grow(c->lstart, cap, ncell + 1, "lstart")))
+    if ((rc = grow(c->count, cap, nbin + 1, "count")) || (cap = 0, rc = grow(c->start, cap, nbin + 1, "start")) ||
+        (cap = 0, rc = grow(c->lstart, cap, nbin + 1, "lstart")))
       return rc;
-    c->cap_cell = ncell + 1;
+    c->cap_cell = nbin + 1;
   }
-  const int64_t nb = (ncell + 1023) / 1024 + 1;
+  if (sub && (rc = grow(c->cstart, c->cap_cstart, ncell + 1, "cstart"))) return rc;
+  const int64_t nb = (nbin + 1023) / 1024 + 1;
   if (nb > capB) {
     int64_t cap = 0;
     c->cap_blocks = 0;
@@ -448,11 +454,13 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
   }
   c->N = N;
   c->ncell = ncell;
+  c->sub = sub;
   for (int k = 0; k < 3; ++k) c->nc[k] = nc[k], c->box[k] = box[k];
   c->nvec = nvec;
   c->model = m;
   c->built = false;
   const double inv_h[3] = {(double)nc[0] / box[0], (double)nc[1] / box[1], (double)nc[2] / box[2]};
+  const double inv_hh[3] = {(double)(2 * nc[0]) / box[0], (double)(2 * nc[1]) / box[1], (double)(2 * nc[2]) / box[2]};
   hipEvent_t ev;
   prof_begin(m, PROF_BUILD, s, &ev);
   const int32_t *order = nullptr;
@@ -460,7 +468,7 @@ int md_build_cells(md_model *m, md_cells *c, const double *pos, const double *qu
     std::swap(c->perm, c->perm_prev);
     order = c->perm_prev;
   }
-  rc = launch_build(m, c, pos, quat, m->host.ncomp > 1 ? comp : nullptr, N, inv_h, order, s);
+  rc = launch_build(m, c, pos, quat, m->host.ncomp > 1 ? comp : nullptr, N, inv_h, inv_hh, order, s);
   prof_end(m, PROF_BUILD, s, ev);
   if (rc) return rc;
   c->order = order;
@@ -659,7 +667,7 @@ int md_long_range_correction(const md_component_desc *comps, int32_t ncomp, cons
   if (ncomp > MD_MAX_COMP) return set_error(MD_ECOMP, "md_long_range_correction: ncomp exceeds MD_MAX_COMP");
   if (!std::isfinite(rc)) return set_error(MD_ENONFINITE, "md_long_range_correction: r_c not finite");
   if (!(rc > 0.0)) return set_error(MD_EINVAL, "md_long_range_correction: r_c <= 0");
-  if (flags & ~(MD_LJ_SHIFT | MD_CHECK | MD_HALF_SHELL))
+  if (flags & ~(MD_LJ_SHIFT | MD_CHECK | MD_HALF_SHELL | MD_SUBCELLS))
     return set_error(MD_EINVAL, "md_long_range_correction: unknown flag");
   double V = 1.0;
   for (int k = 0; k < 3; ++k) {

@@ -25,12 +25,19 @@ struct BinArgs {
   const int32_t *comp, *order;  // order: visiting order (the previous build's permutation) or NULL
   int64_t N;
   double Lx, Ly, Lz, ihx, ihy, ihz;
-  int32_t nx, ny, nz, ncomp, check_quat;
+  double ihx2, ihy2, ihz2;  // 2 n_k / L_k: half-edge cells (sub)
+  int32_t nx, ny, nz, ncomp, check_quat, sub;
   int32_t *cellv, *slotv, *count, *status;
 };
 
-// Wrap + bin + per-cell histogram.  Position d of the visiting order takes molecule order[d]
-// (identity without an order) and writes its cell and provisional slot at position d (coalesced).
+// Low bit of the half-edge cell index min(2 n - 1, floor(xw * (2 n / L))) along one axis: which
+// half of its cell the coordinate lies in.
+__device__ __forceinline__ int half_bit(double xw, double inv_hh, int n) { return bin1(xw, inv_hh, 2 * n) & 1; }
+
+// Wrap + bin + per-bin histogram (a bin is a cell, or with half-edge cells the half-cell 8 cell +
+// octant, octant 4 z + 2 y + x from the low bits of the half-cell coordinates).  Position d of
+// the visiting order takes molecule order[d] (identity without an order) and writes its bin and
+// provisional slot at position d (coalesced).
 // In the previous build's order neighbouring positions mostly fall into the same cell, and each
 // run of equal cells inside a wavefront takes one atomic add.  The blocks of each XCD (block b
 // runs on XCD b % 8) take one contiguous eighth of the positions, so the COM lines a region of
@@ -57,13 +64,17 @@ __global__ __launch_bounds__(256) void k_bin(BinArgs a) {
     if (!(fabs(n2 - 1.0) <= 1e-6)) flags |= MD_DEV_QUAT;
   }
   if (flags && valid) atomicOr(a.status, flags);
-  const int cx = bin1(wrap1(x, a.Lx), a.ihx, a.nx);
-  const int cy = bin1(wrap1(y, a.Ly), a.ihy, a.ny);
-  const int cz = bin1(wrap1(z, a.Lz), a.ihz, a.nz);
+  const double xw = wrap1(x, a.Lx), yw = wrap1(y, a.Ly), zw = wrap1(z, a.Lz);
+  const int cx = bin1(xw, a.ihx, a.nx);
+  const int cy = bin1(yw, a.ihy, a.ny);
+  const int cz = bin1(zw, a.ihz, a.nz);
   // a molecule with a non-finite coordinate goes to cell i mod ncell, so that such molecules
   // (a run that blew up) spread over the grid instead of crowding one cell; its sorted copy is
   // NaN, which fails every cutoff test, so it has no partners
-  const int cell = !valid ? -1 : (finite ? (cz * a.ny + cy) * a.nx + cx : (int)(i % (int64_t)(a.nx * a.ny * a.nz)));
+  int cell = !valid ? -1 : (finite ? (cz * a.ny + cy) * a.nx + cx : (int)(i % (int64_t)(a.nx * a.ny * a.nz)));
+  if (a.sub && valid)
+    cell = 8 * cell + (finite ? 4 * half_bit(zw, a.ihz2, a.nz) + 2 * half_bit(yw, a.ihy2, a.ny) + half_bit(xw, a.ihx2, a.nx)
+                              : 0);
   // runs of equal cells among consecutive lanes: the run head adds the run length
   const int prev = __shfl_up(cell, 1, 64);
   const bool head = lane == 0 || prev != cell;
@@ -127,8 +138,9 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_local(int32_t *in, int64_
 }
 
 // Exclusive scan of the nb tile totals in place (one block, sequential over chunks), total to
-// out[n].
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(int32_t *bsum, int64_t nb, int32_t *out, int64_t n) {
+// out[n] (and to out2[n2] when given).
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(int32_t *bsum, int64_t nb, int32_t *out, int64_t n,
+                                                           int32_t *out2, int64_t n2) {
   __shared__ int wsum[SCAN_THREADS / 64];
   __shared__ int carry_s;
   if (threadIdx.x == 0) carry_s = 0;
@@ -148,28 +160,36 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(int32_t *bsum, int64_
     if (threadIdx.x == SCAN_THREADS - 1) carry_s = carry + woff + incl;
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[n] = carry_s;
+  if (threadIdx.x == 0) {
+    out[n] = carry_s;
+    if (out2) out2[n2] = carry_s;
+  }
 }
 
 // ---------------------------------------------------------------- stable placement + gather
-// Cell start = tile-local prefix + scanned tile total: thread t < ncell writes start[t]; visiting
-// position t < N places its molecule at its provisional slot of its cell (both read only lstart
-// and bsum).
+// Bin start = tile-local prefix + scanned tile total: thread t < nbin writes start[t] (and, with
+// half-edge cells, the cell start cstart[t / 8] from every eighth bin); visiting position t < N
+// places its molecule at its provisional slot of its bin (both read only lstart and bsum).
 __global__ __launch_bounds__(256) void k_scatter(const int32_t *cellv, const int32_t *slotv, const int32_t *order,
-                                                 const int32_t *lstart, const int32_t *bsum, int64_t N, int64_t ncell,
-                                                 int32_t *start, int32_t *tmp) {
+                                                 const int32_t *lstart, const int32_t *bsum, int64_t N, int64_t nbin,
+                                                 int32_t *start, int32_t *cstart, int32_t *tmp) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < ncell) start[t] = lstart[t] + bsum[t / SCAN_TILE];
+  if (t < nbin) {
+    const int32_t v = lstart[t] + bsum[t / SCAN_TILE];
+    start[t] = v;
+    if (cstart && (t & 7) == 0) cstart[t >> 3] = v;
+  }
   if (t < N) {
     const int c = cellv[t];
     tmp[lstart[c] + bsum[c / SCAN_TILE] + slotv[t]] = order ? order[t] : (int32_t)t;
   }
 }
 
-// The caller-order cell ids of the view: cell_of[order[d]] = cellv[d].
-__global__ void k_cell_of(const int32_t *cellv, const int32_t *order, int64_t N, int32_t *cell_of) {
+// The caller-order cell ids of the view: cell_of[order[d]] = cellv[d] (its bin, shifted right by
+// 3 when the bins are half-edge cells).
+__global__ void k_cell_of(const int32_t *cellv, const int32_t *order, int64_t N, int shift, int32_t *cell_of) {
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (d < N) cell_of[order ? order[d] : d] = cellv[d];
+  if (d < N) cell_of[order ? order[d] : d] = cellv[d] >> shift;
 }
 
 struct GatherArgs {
@@ -190,9 +210,9 @@ __device__ __forceinline__ void rotate(const double q[4], const double v[3], dou
   o[2] = 2.0 * (x * z - w * y) * v[0] + 2.0 * (y * z + w * x) * v[1] + (w * w - x * x - y * y + z * z) * v[2];
 }
 
-// Final position of molecule i inside its cell = number of molecules of the same cell with a
+// Final position of molecule i inside its bin = number of molecules of the same bin with a
 // smaller original index (a stable counting sort whatever order the atomic slots came in); then
-// gather the sorted copies.  The cell's entries are contiguous in tmp, so the ranking reads
+// gather the sorted copies.  The bin's entries are contiguous in tmp, so the ranking reads
 // cached words only.  Thread d takes molecule order[d] (identity without an order): in the
 // previous build's order the sorted copies are written nearly in sequence.  The blocks of each
 // XCD (block b runs on XCD b % 8) take one contiguous eighth of that order, so the COM lines a
@@ -275,7 +295,7 @@ inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 }  // namespace
 
 int launch_cell_of(const md_cells *c, hipStream_t s) {
-  k_cell_of<<<nblk(c->N, 256), 256, 0, s>>>(c->cellv, c->order, c->N, c->cell_of);
+  k_cell_of<<<nblk(c->N, 256), 256, 0, s>>>(c->cellv, c->order, c->N, c->sub ? 3 : 0, c->cell_of);
   return check_hip(hipGetLastError(), "k_cell_of");
 }
 
@@ -298,25 +318,27 @@ int launch_scale_copy(const double *src, double *dst, int64_t n, double a, hipSt
 }
 
 int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat, const int32_t *comp, int64_t N,
-                 const double inv_h[3], const int32_t *order, hipStream_t s) {
+                 const double inv_h[3], const double inv_hh[3], const int32_t *order, hipStream_t s) {
   int rc;
   // the histogram must start at zero: left so by the previous build's scan, else cleared here
-  // (whole allocation, so a later build with more cells also starts from zero)
+  // (whole allocation, so a later build with more bins also starts from zero)
   if (!c->counts_zero && (rc = launch_fill_i32(c->count, c->cap_cell, 0, s))) return rc;
   c->counts_zero = false;
-  BinArgs b{pos,      quat,      comp,      order,    N,        c->box[0],       c->box[1],
-            c->box[2], inv_h[0], inv_h[1], inv_h[2], c->nc[0],        c->nc[1],
-            c->nc[2], m->host.ncomp, (int32_t)((m->flags & MD_CHECK) != 0), c->cellv, c->slot, c->count,
-            m->status};
+  const int64_t nbin = c->sub ? 8 * c->ncell : c->ncell;
+  BinArgs b{pos,       quat,      comp,      order,     N,         c->box[0],     c->box[1],
+            c->box[2], inv_h[0],  inv_h[1],  inv_h[2],  inv_hh[0], inv_hh[1],     inv_hh[2],
+            c->nc[0],  c->nc[1],  c->nc[2],  m->host.ncomp, (int32_t)((m->flags & MD_CHECK) != 0), (int32_t)c->sub,
+            c->cellv,  c->slot,   c->count,  m->status};
   k_bin<<<(unsigned)pair_blocks(nblk(N, 256)), 256, 0, s>>>(b);
   if ((rc = check_hip(hipGetLastError(), "k_bin"))) return rc;
-  const int64_t nb = (c->ncell + SCAN_TILE - 1) / SCAN_TILE;
-  k_scan_local<<<(unsigned)nb, SCAN_THREADS, 0, s>>>(c->count, c->ncell, c->lstart, c->bsum);
-  k_scan_top<<<1, SCAN_THREADS, 0, s>>>(c->bsum, nb, c->start, c->ncell);
+  const int64_t nb = (nbin + SCAN_TILE - 1) / SCAN_TILE;
+  k_scan_local<<<(unsigned)nb, SCAN_THREADS, 0, s>>>(c->count, nbin, c->lstart, c->bsum);
+  k_scan_top<<<1, SCAN_THREADS, 0, s>>>(c->bsum, nb, c->start, nbin, c->sub ? c->cstart : nullptr, c->ncell);
   if ((rc = check_hip(hipGetLastError(), "k_scan"))) return rc;
   c->counts_zero = true;
-  k_scatter<<<nblk(std::max<int64_t>(N, c->ncell), 256), 256, 0, s>>>(c->cellv, c->slot, order, c->lstart, c->bsum,
-                                                                      N, c->ncell, c->start, c->tmp);
+  k_scatter<<<nblk(std::max<int64_t>(N, nbin), 256), 256, 0, s>>>(c->cellv, c->slot, order, c->lstart, c->bsum, N,
+                                                                   nbin, c->start, c->sub ? c->cstart : nullptr,
+                                                                   c->tmp);
   if ((rc = check_hip(hipGetLastError(), "k_scatter"))) return rc;
   GatherArgs g{pos, m->single_site ? nullptr : quat, comp, c->cellv, c->start, c->tmp, order, N,
                c->box[0], c->box[1], c->box[2], m->dev, m->shape.lj, m->shape.chg, m->shape.dip, m->shape.quad,

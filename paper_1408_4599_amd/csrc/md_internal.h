@@ -59,6 +59,9 @@ struct ModelDev {
 // Everything a pair kernel needs about the sorted configuration.
 struct CellsDev {
   const int32_t *cell_start, *perm, *scomp;
+  // with half-edge cells: first sorted slot of half-cell 8 c + octant (octant 4 z + 2 y + x),
+  // [8 ncell + 1]; else NULL
+  const int32_t *sub_start;
   const double *sx, *sy, *sz;  // wrapped COMs in sorted order
   const double *svec;          // [N][nvec][3] world-frame site offsets / axes, sorted order
   const double *squat;         // [N][4] quaternions in sorted order (multi-site models), or NULL
@@ -114,6 +117,11 @@ struct md_cells {
   const int32_t *order = nullptr;
   bool cell_of_valid = false;
   int32_t *perm_prev = nullptr;  // the other buffer of the permutation pair (previous build's order)
+  // counting-sort bins: the cells, or with half-edge cells (sub) the 8 half-cells of each cell
+  // (bin 8 c + octant); start has one entry per bin plus the total, cstart the cell starts then
+  bool sub = false;
+  int32_t *cstart = nullptr;
+  int64_t cap_cstart = 0;
   int32_t *count = nullptr, *start = nullptr, *bsum = nullptr;
   int32_t *lstart = nullptr;     // tile-local exclusive prefix of the counts
   bool counts_zero = false;      // every entry of the count allocation is zero (left so by the scan)
@@ -151,7 +159,8 @@ struct md_model {
   hipStream_t side = nullptr;
   hipEvent_t ev_leap[2] = {nullptr, nullptr}, ev_red[2] = {nullptr, nullptr};
   int lds_limit = 0;            // LDS bytes per block on the model's device (queried at first use)
-  int lj1_static_lds[2] = {-1, -1};  // static LDS of the single-site pair kernel (FP64, FP32)
+  int lj1_static_lds[4] = {-1, -1, -1, -1};  // static LDS of the single-site pair kernel (FP64, FP32;
+                                             // then with half-edge cells)
   // profiling
   bool profiling = false;
   struct Ev {
@@ -177,7 +186,7 @@ void prof_end(md_model *m, int group, hipStream_t s, hipEvent_t a);
 
 // launchers
 int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat, const int32_t *comp, int64_t N,
-                 const double inv_h[3], const int32_t *order, hipStream_t s);
+                 const double inv_h[3], const double inv_hh[3], const int32_t *order, hipStream_t s);
 int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o, hipStream_t s, int64_t *nblocks);
 int launch_reduce(md_model *m, int64_t nrows, int ncols, const double *rows, double *out, hipStream_t s);
 // pair partial rows -> uw[0..4] (U, W, W_aa), pair count, energies row; with kin_rows (the

@@ -261,9 +261,18 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_pair_lj(CellsDev c, LJK k, PairOut o, int cap, int lcap) {
+// SUB: half-edge cells.  The molecules of each cell come sorted by half-edge cell (lower z-half
+// first), the tile is staged in the order (y row, z half-layer, x) and a home molecule in z-half b
+// walks, in each of its three y rows, the five z half-layers [2 hz + b, 2 hz + b + 5) of the eight
+// (tile z half-layers 2 hz .. 2 hz + 5 surround home cell hz): the sixth lies more than one cell
+// edge (>= r_c) away along z, so none of its pairs is inside the cutoff.  Each lane's range starts
+// at its molecule's half; the runs all lanes fill are walked unchecked, the rest bounds-checked.
+template <typename R, bool SUB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_pair_lj(CellsDev c, LJK k, PairOut o, int cap, int lcap) {
   constexpr bool F32 = std::is_same<R, float>::value;
+  // staged groups: tile cells (3 x 4 x 4, cell u = ux + 3 uy + 12 uz), or with SUB the cell halves
+  // in the order g = (uy * 8 + z half-layer) * 3 + ux
+  constexpr int NG = SUB ? 2 * QCELLS : QCELLS;
   extern __shared__ double dyn[];
   // LDS: [FP32 tile: cap float4 (FP32 path)] [FP64 tile: cap x 3 doubles] [per-lane lists: 256 x
   // lcap]; list entries are staged slots (16 bit)
@@ -272,8 +281,11 @@ __global__ __launch_bounds__(256) void k_pair_lj(CellsDev c, LJK k, PairOut o, i
   __attribute__((address_space(3))) f4v *const l32 = (__attribute__((address_space(3))) f4v *)t32;
   __attribute__((address_space(3))) double *const l64 = (__attribute__((address_space(3))) double *)t64;
   unsigned short *const lists = (unsigned short *)(t64 + 3 * cap);
-  __shared__ int qoff[QCELLS + 1], qstart[QCELLS];
-  __shared__ double qsh[QCELLS][3];
+  // per group: first tile slot (qoff, plus the total), first sorted index (qstart), image shift
+  // (qsh; SUB: packed as qcode, each axis shift / L + 1 in two bits)
+  __shared__ int qoff[NG + 1], qstart[NG];
+  __shared__ double qsh[SUB ? 1 : QCELLS][3];
+  __shared__ int qcode[SUB ? NG : 1];
   __shared__ double red[4][5];
   // neighbour table of the chunked path, in the (then unused) list area
   NbTable &nb = *(NbTable *)lists;
@@ -287,27 +299,51 @@ __global__ __launch_bounds__(256) void k_pair_lj(CellsDev c, LJK k, PairOut o, i
     // tile cell u = ux + 3 uy + 12 uz covers cell (bx - 1 + ux, 2 by - 1 + uy, 2 bz - 1 + uz)
     if (tid < 64) {
       int cnt = 0;
+      int ux = 0, uy = 0, uz = 0, s0 = 0, s1 = 0, sm = 0, code = 0;
+      double shx = 0.0, shy = 0.0, shz = 0.0;
       if (tid < QCELLS) {
-        int x = bx - 1 + tid % 3, y = 2 * by - 1 + (tid / 3) % 4, z = 2 * bz - 1 + tid / 12;
-        double shx = 0.0, shy = 0.0, shz = 0.0;
-        if (x < 0) x += c.nx, shx = -c.Lx;
-        else if (x >= c.nx) x -= c.nx, shx = c.Lx;
-        if (y < 0) y += c.ny, shy = -c.Ly;
-        else if (y >= c.ny) y -= c.ny, shy = c.Ly;
-        if (z < 0) z += c.nz, shz = -c.Lz;
-        else if (z >= c.nz) z -= c.nz, shz = c.Lz;
+        ux = tid % 3, uy = (tid / 3) % 4, uz = tid / 12;
+        int x = bx - 1 + ux, y = 2 * by - 1 + uy, z = 2 * bz - 1 + uz;
+        int kx = 1, ky = 1, kz = 1;
+        if (x < 0) x += c.nx, shx = -c.Lx, kx = 0;
+        else if (x >= c.nx) x -= c.nx, shx = c.Lx, kx = 2;
+        if (y < 0) y += c.ny, shy = -c.Ly, ky = 0;
+        else if (y >= c.ny) y -= c.ny, shy = c.Ly, ky = 2;
+        if (z < 0) z += c.nz, shz = -c.Lz, kz = 0;
+        else if (z >= c.nz) z -= c.nz, shz = c.Lz, kz = 2;
+        code = kx | ky << 2 | kz << 4;
         const int cc = (z * c.ny + y) * c.nx + x;
-        const int s0 = c.cell_start[cc];
-        cnt = c.cell_start[cc + 1] - s0;
-        qstart[tid] = s0;
-        qsh[tid][0] = shx, qsh[tid][1] = shy, qsh[tid][2] = shz;
+        if constexpr (SUB) {
+          s0 = c.sub_start[8 * cc], sm = c.sub_start[8 * cc + 4], s1 = c.sub_start[8 * cc + 8];
+        } else {
+          s0 = c.cell_start[cc];
+          cnt = c.cell_start[cc + 1] - s0;
+        }
       }
-      const int incl = wave_incl_scan(cnt);
-      if (tid < QCELLS) qoff[tid] = incl - cnt;
-      if (tid == QCELLS - 1) qoff[QCELLS] = incl;
+      if constexpr (SUB) {
+        // the cell's lower and upper z-halves are groups g and g + 3; counts first, then the scan
+        // over lane l's groups 2 l, 2 l + 1 (g order)
+        const int g = (uy * 8 + 2 * uz) * 3 + ux;
+        if (tid < QCELLS) {
+          qoff[g] = sm - s0, qoff[g + 3] = s1 - sm;
+          qstart[g] = s0, qstart[g + 3] = sm;
+          qcode[g] = code, qcode[g + 3] = code;
+        }
+        wave_sync_lds();
+        const int c0 = tid < QCELLS ? qoff[2 * tid] : 0, c1 = tid < QCELLS ? qoff[2 * tid + 1] : 0;
+        wave_sync_lds();
+        const int incl = wave_incl_scan(c0 + c1);
+        if (tid < QCELLS) qoff[2 * tid] = incl - c0 - c1, qoff[2 * tid + 1] = incl - c1;
+        if (tid == QCELLS - 1) qoff[NG] = incl;
+      } else {
+        if (tid < QCELLS) qstart[tid] = s0, qsh[tid][0] = shx, qsh[tid][1] = shy, qsh[tid][2] = shz;
+        const int incl = wave_incl_scan(cnt);
+        if (tid < QCELLS) qoff[tid] = incl - cnt;
+        if (tid == QCELLS - 1) qoff[QCELLS] = incl;
+      }
     }
     __syncthreads();
-    const int U = qoff[QCELLS];
+    const int U = qoff[NG];
     // tile centre: origin of the FP32 coordinates
     const double ox = (bx + 0.5) * c.hx, oy = (2 * by + 1) * c.hy, oz = (2 * bz + 1) * c.hz;
     // stage entry: FP64 shifted position (x, y, z) at slot e, FP32 centre-relative copy and norm
@@ -318,21 +354,70 @@ __global__ __launch_bounds__(256) void k_pair_lj(CellsDev c, LJK k, PairOut o, i
         t32[e] = f4v{fx, fy, fz, fmaf(fz, fz, fmaf(fy, fy, fx * fx))};
       }
     };
-    auto stage = [&](int e, int src, int cc) {
-      put(e, c.sx[src] + qsh[cc][0], c.sy[src] + qsh[cc][1], c.sz[src] + qsh[cc][2]);
+    // image shift of group g (exact: 0 or +-L)
+    auto shift = [&](int g, double &sx, double &sy, double &sz) {
+      if constexpr (SUB) {
+        const int q = qcode[g];
+        sx = (double)((q & 3) - 1) * c.Lx, sy = (double)(((q >> 2) & 3) - 1) * c.Ly;
+        sz = (double)((q >> 4) - 1) * c.Lz;
+      } else {
+        sx = qsh[g][0], sy = qsh[g][1], sz = qsh[g][2];
+      }
     };
-    // this wavefront's home cell: tile cell uh (unshifted, since it lies inside the box)
+    auto stage = [&](int e, int src, int g) {
+      double sx, sy, sz;
+      shift(g, sx, sy, sz);
+      put(e, c.sx[src] + sx, c.sy[src] + sy, c.sz[src] + sz);
+    };
+    // SUB: the group of tile slot e among groups [glo, glo + n), n <= 32 (the last one whose first
+    // slot is <= e; empty groups are passed over)
+    auto group_of = [&](int e, int glo, int n) {
+      int g = glo;
+#pragma unroll
+      for (int st = 16; st > 0; st >>= 1)
+        if (g + st < glo + n && qoff[g + st] <= e) g += st;
+      return g;
+    };
+    // this wavefront's home cell: tile cell uh (unshifted, since it lies inside the box); SUB: its
+    // halves are groups gh and gh + 3
     const int hy = wave & 1, hz = wave >> 1;
     const bool hvalid = 2 * by + hy < c.ny && 2 * bz + hz < c.nz;
     const int uh = 1 + 3 * (hy + 1) + 12 * (hz + 1);
-    const int hn = hvalid ? __builtin_amdgcn_readfirstlane(qoff[uh + 1] - qoff[uh]) : 0;
-    const int hs = qstart[uh];
+    const int gh = ((hy + 1) * 8 + 2 * (hz + 1)) * 3 + 1;
+    const int hlow = SUB ? qoff[gh + 1] - qoff[gh] : 0;  // molecules in the lower z-half
+    const int hn = !hvalid ? 0
+                   : SUB ? __builtin_amdgcn_readfirstlane(hlow + qoff[gh + 4] - qoff[gh + 3])
+                         : __builtin_amdgcn_readfirstlane(qoff[uh + 1] - qoff[uh]);
+    const int hs = SUB ? qstart[gh] : qstart[uh];
     if (!__syncthreads_or(hn > 64)) {
       // the walk reads up to 4 NS - 1 <= 31 entries past a segment (results discarded), so the
       // tile needs that much slack
       const bool tiled = U + SLACK <= cap;  // block-uniform
       const int orig32 = lane < hn ? c.perm[hs + lane] : 0;
-      if (tiled) {
+      if (tiled && SUB) {
+        // wave w stages y row w (groups 24 w .. 24 w + 23), the first 128 entries loaded before
+        // any is stored
+        const int gb = 24 * wave, e0 = qoff[gb], e1 = qoff[gb + 24];
+        double vx[2], vy[2], vz[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int e = e0 + 64 * q + lane;
+          if (e < e1) {
+            const int g = group_of(e, gb, 24), src = qstart[g] + (e - qoff[g]);
+            double sx, sy, sz;
+            shift(g, sx, sy, sz);
+            vx[q] = c.sx[src] + sx, vy[q] = c.sy[src] + sy, vz[q] = c.sz[src] + sz;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          if (e0 + 64 * q + lane < e1) put(e0 + 64 * q + lane, vx[q], vy[q], vz[q]);
+        for (int e = e0 + 128 + lane; e < e1; e += 64) {
+          const int g = group_of(e, gb, 24);
+          stage(e, qstart[g] + (e - qoff[g]), g);
+        }
+        __syncthreads();
+      } else if (tiled) {
         // stage by x-rows of three cells (contiguous in the sorted arrays unless x wraps): wave w
         // takes rows w, w + 4, w + 8, w + 12, the first 64 entries of all four rows loaded
         // before any is stored (one round of global-load latency), longer rows after
@@ -371,7 +456,9 @@ __global__ __launch_bounds__(256) void k_pair_lj(CellsDev c, LJK k, PairOut o, i
       double sfx = 0.0, sfy = 0.0, sfz = 0.0, su = 0.0, swx = 0.0, swy = 0.0, swz = 0.0;
       int sn = 0;
       if (hn > 0) {
-        const int self = qoff[uh] + il;
+        // tile slot of this lane's molecule; SUB: its z-half zb (lower half first in the cell)
+        const int zb = SUB && il >= hlow ? 1 : 0;
+        const int self = SUB ? qoff[gh + 3 * zb] + il - zb * hlow : qoff[uh] + il;
         // this lane's molecule: FP64 position, FP32 test operands (idle lanes: far away)
         double xi = 1e30, yi = 1e30, zi = 1e30;
         float ax = 0.0f, ay = 0.0f, az = 0.0f, thri = -1.0f;
@@ -396,9 +483,9 @@ __global__ __launch_bounds__(256) void k_pair_lj(CellsDev c, LJK k, PairOut o, i
             (__attribute__((address_space(3))) unsigned short *)wlist + lane;
         __attribute__((address_space(3))) unsigned short *lp = mylist;
         __attribute__((address_space(3))) unsigned short *const lplim = mylist + 64 * (lcap - 2);
-        // pass 2: every lane evaluates its own list in order.  (Splitting each molecule's hits
-        // evenly over its lanes evens out their counts but needs a buffer per molecule, and the
-        // LDS it takes costs a resident block per CU, more than the balance gains.)
+        // pass 2: every lane evaluates its own list in order.  (Sharing each molecule's hits evenly
+        // over its lanes, through the lists' lengths and end markers, measured slower: its
+        // bookkeeping per flush and per hit costs more than the shorter longest list saves.)
         // FP64 path: one set of FP64 sums for the whole walk; FP32 path: FP32 sums per flush,
         // promoted to the lane's FP64 sums (cascaded summation)
         LJFlush<double> a64;
@@ -424,82 +511,143 @@ __global__ __launch_bounds__(256) void k_pair_lj(CellsDev c, LJK k, PairOut o, i
           lp = mylist;
         };
         const int sla = act ? sl : 0;  // idle lanes walk with slice 0
-        for (int d = 0; d < 3; ++d) {
-          const int u0 = 3 * hy + 12 * (hz + d);
-          const int lo = __builtin_amdgcn_readfirstlane(qoff[u0]), hi = __builtin_amdgcn_readfirstlane(qoff[u0 + 9]);
+        // candidate pair (slots t, t + 1): FP32 test operands, or FP64 positions
+        using V = typename std::conditional<F32, f4v, double>::type;
+        struct Cand {
+          V a0, a1, a2, b0, b1, b2;
+        };
+        auto load = [&](Cand &q, int t) {
+          if constexpr (F32) {
+            q.a0 = l32[t], q.b0 = l32[t + 1];
+          } else {
+            q.a0 = l64[3 * t], q.a1 = l64[3 * t + 1], q.a2 = l64[3 * t + 2];
+            q.b0 = l64[3 * t + 3], q.b1 = l64[3 * t + 4], q.b2 = l64[3 * t + 5];
+          }
+        };
+        // test the pair at slot t, list the hits (the slot is always written; the count advances
+        // on a hit); lim: slots at or past it are not candidates (checked steps only)
+        auto step = [&](const Cand &q, int t, int sself, int lim, auto tail, auto home) {
+          bool ha, hb;
+          if constexpr (F32) {
+            ha = fmaf(az, q.a0.z, fmaf(ay, q.a0.y, fmaf(ax, q.a0.x, q.a0.w))) < thri;
+            hb = fmaf(az, q.b0.z, fmaf(ay, q.b0.y, fmaf(ax, q.b0.x, q.b0.w))) < thri;
+          } else {
+            const double pax = xi - q.a0, pay = yi - q.a1, paz = zi - q.a2;
+            const double pbx = xi - q.b0, pby = yi - q.b1, pbz = zi - q.b2;
+            ha = fma(paz, paz, fma(pay, pay, pax * pax)) < rc2;
+            hb = fma(pbz, pbz, fma(pby, pby, pbx * pbx)) < rc2;
+          }
+          if (tail) ha = ha && t < lim, hb = hb && t + 1 < lim;
+          if (home) ha = ha && t != sself, hb = hb && t + 1 != sself;
+          *lp = (unsigned short)t;
+          lp += ha ? 64 : 0;
+          *lp = (unsigned short)(t + 1);
+          lp += hb ? 64 : 0;
+          if (__any(lp > lplim)) flush();
+        };
+        // wave-uniform range [cs, ce) of tile indices, staged at slot = index - off: slice s tests
+        // the adjacent slots 2 s, 2 s + 1 of every run of 2 NS candidates, two runs per trip with
+        // the next run's pair loaded before the current one is tested.  The walk reads up to
+        // 2 NS - 1 slots past the range (the tile keeps SLACK spare entries); only the last,
+        // partial run is bounds-checked, and only the home layer holds the molecule itself.
+        auto walk = [&](int cs, int ce, int off, auto home) {
+          int sa = cs + 2 * sla - off;  // slot of this lane's first candidate
+          const int send = ce - off, sself = self - off;
+          Cand A, B;
+          load(A, sa);
+          int kb = cs;
+          for (; kb + 4 * NS <= ce; kb += 4 * NS, sa += 4 * NS) {
+            load(B, sa + 2 * NS);
+            step(A, sa, sself, send, std::false_type(), home);
+            load(A, sa + 4 * NS);
+            step(B, sa + 2 * NS, sself, send, std::false_type(), home);
+          }
+          if (kb + 2 * NS <= ce) {
+            step(A, sa, sself, send, std::false_type(), home);
+            kb += 2 * NS, sa += 2 * NS;
+            if (kb < ce) load(A, sa);
+          }
+          if (kb < ce) step(A, sa, sself, send, std::true_type(), home);
+        };
+        // SUB, whole tile staged: this lane's range [rs, re) of tile slots; the first nf runs are
+        // full for every lane, the others up to nall are checked.  Loads are kept inside the tile
+        // (a clamped load only feeds checked, uncounted candidates).
+        auto walk_lane = [&](int rs, int re, int nf, int nall, auto home) {
+          const int tlim = cap - 2;
+          int sa = rs + 2 * sla;
+          Cand A, B;
+          load(A, min(sa, tlim));
+          int j = 0;
+          for (; j + 2 <= nf; j += 2, sa += 4 * NS) {
+            load(B, sa + 2 * NS);
+            step(A, sa, self, re, std::false_type(), home);
+            load(A, min(sa + 4 * NS, tlim));
+            step(B, sa + 2 * NS, self, re, std::false_type(), home);
+          }
+          if (j < nf) {
+            step(A, sa, self, re, std::false_type(), home);
+            ++j, sa += 2 * NS;
+            load(A, min(sa, tlim));
+          }
+          for (; j < nall; ++j, sa += 2 * NS) {
+            step(A, sa, self, re, std::true_type(), home);
+            load(A, min(sa + 2 * NS, tlim));
+          }
+        };
+        // one range of tile indices [lo, hi): walked at once when the whole tile is staged, else
+        // through the window, [cs, ce) at a time, the previous window flushed first (lk: source
+        // group of tile index e)
+        auto segments = [&](int lo, int hi, auto lk, auto home) {
           for (int cs = lo, ce; cs < hi; cs = ce) {
             ce = tiled ? hi : min(hi, cs + C);
             const int off = tiled ? 0 : cs - wb;  // slot = tile index - off
             if (!tiled) {
-              // stage [cs, ce) of this segment into the window; the previous window is flushed
               flush();
               for (int e = cs + lane; e < ce; e += 64) {
-                int u = u0;
-                while (e >= qoff[u + 1]) ++u;
-                stage(e - off, qstart[u] + (e - qoff[u]), u);
+                const int g = lk(e);
+                stage(e - off, qstart[g] + (e - qoff[g]), g);
               }
               wave_sync_lds();
             }
-            // candidate pair (slots t, t + 1): FP32 test operands, or FP64 positions
-            using V = typename std::conditional<F32, f4v, double>::type;
-            struct Cand {
-              V a0, a1, a2, b0, b1, b2;
+            walk(cs, ce, off, home);
+          }
+        };
+        if constexpr (SUB) {
+          // y rows hy .. hy + 2 of the tile; in row uy the groups of z half-layer 2 hz onwards start
+          // at gy = 24 uy + 6 hz, a lane in z-half zb walks [qoff[gy + 3 zb], qoff[gy + 3 zb + 15])
+          if (tiled) {
+            for (int r = 0; r < 3; ++r) {
+              const int gy = 24 * (hy + r) + 6 * hz;
+              const int l0 = __builtin_amdgcn_readfirstlane(qoff[gy + 15] - qoff[gy]);
+              const int l1 = __builtin_amdgcn_readfirstlane(qoff[gy + 18] - qoff[gy + 3]);
+              const int rs = qoff[gy + 3 * zb], re = qoff[gy + 3 * zb + 15];
+              const int nf = div_small(min(l0, l1), r2ns), nall = div_small(max(l0, l1) + 2 * NS - 1, r2ns);
+              if (r == 1) walk_lane(rs, re, nf, nall, std::true_type());
+              else walk_lane(rs, re, nf, nall, std::false_type());
+            }
+          } else {
+            // the window holds uniform ranges: all six half-layers of each row, nothing culled
+            for (int r = 0; r < 3; ++r) {
+              const int gy = 24 * (hy + r) + 6 * hz;
+              const int lo = __builtin_amdgcn_readfirstlane(qoff[gy]);
+              const int hi = __builtin_amdgcn_readfirstlane(qoff[gy + 18]);
+              auto lk = [&](int e) { return group_of(e, 24 * (hy + r), 24); };
+              if (r == 1) segments(lo, hi, lk, std::true_type());
+              else segments(lo, hi, lk, std::false_type());
+            }
+          }
+        } else {
+          for (int d = 0; d < 3; ++d) {
+            const int u0 = 3 * hy + 12 * (hz + d);
+            const int lo = __builtin_amdgcn_readfirstlane(qoff[u0]);
+            const int hi = __builtin_amdgcn_readfirstlane(qoff[u0 + 9]);
+            auto lk = [&](int e) {
+              int u = u0;
+              while (e >= qoff[u + 1]) ++u;
+              return u;
             };
-            auto load = [&](Cand &q, int t) {
-              if constexpr (F32) {
-                q.a0 = l32[t], q.b0 = l32[t + 1];
-              } else {
-                q.a0 = l64[3 * t], q.a1 = l64[3 * t + 1], q.a2 = l64[3 * t + 2];
-                q.b0 = l64[3 * t + 3], q.b1 = l64[3 * t + 4], q.b2 = l64[3 * t + 5];
-              }
-            };
-            // test the pair at slot t, list the hits (the slot is always written; the count
-            // advances on a hit); lim: slots at or past it are not candidates (tail only)
-            auto step = [&](const Cand &q, int t, int sself, int lim, auto tail, auto home) {
-              bool ha, hb;
-              if constexpr (F32) {
-                ha = fmaf(az, q.a0.z, fmaf(ay, q.a0.y, fmaf(ax, q.a0.x, q.a0.w))) < thri;
-                hb = fmaf(az, q.b0.z, fmaf(ay, q.b0.y, fmaf(ax, q.b0.x, q.b0.w))) < thri;
-              } else {
-                const double pax = xi - q.a0, pay = yi - q.a1, paz = zi - q.a2;
-                const double pbx = xi - q.b0, pby = yi - q.b1, pbz = zi - q.b2;
-                ha = fma(paz, paz, fma(pay, pay, pax * pax)) < rc2;
-                hb = fma(pbz, pbz, fma(pby, pby, pbx * pbx)) < rc2;
-              }
-              if (tail) ha = ha && t < lim, hb = hb && t + 1 < lim;
-              if (home) ha = ha && t != sself, hb = hb && t + 1 != sself;
-              *lp = (unsigned short)t;
-              lp += ha ? 64 : 0;
-              *lp = (unsigned short)(t + 1);
-              lp += hb ? 64 : 0;
-              if (__any(lp > lplim)) flush();
-            };
-            // slice s tests the adjacent slots 2 s, 2 s + 1 of every run of 2 NS candidates, two
-            // runs per trip with the next run's pair loaded before the current one is tested.
-            // The walk reads up to 2 NS - 1 slots past the range (the tile keeps SLACK spare
-            // entries); only the last, partial run is bounds-checked, and only the home layer
-            // holds the molecule itself.
-            auto walk = [&](auto home) {
-              int sa = cs + 2 * sla - off;  // slot of this lane's first candidate
-              const int send = ce - off, sself = self - off;
-              Cand A, B;
-              load(A, sa);
-              int kb = cs;
-              for (; kb + 4 * NS <= ce; kb += 4 * NS, sa += 4 * NS) {
-                load(B, sa + 2 * NS);
-                step(A, sa, sself, send, std::false_type(), home);
-                load(A, sa + 4 * NS);
-                step(B, sa + 2 * NS, sself, send, std::false_type(), home);
-              }
-              if (kb + 2 * NS <= ce) {
-                step(A, sa, sself, send, std::false_type(), home);
-                kb += 2 * NS, sa += 2 * NS;
-                if (kb < ce) load(A, sa);
-              }
-              if (kb < ce) step(A, sa, sself, send, std::true_type(), home);
-            };
-            if (d == 1) walk(std::true_type());
-            else walk(std::false_type());
+            if (d == 1) segments(lo, hi, lk, std::true_type());
+            else segments(lo, hi, lk, std::false_type());
           }
         }
         flush();
@@ -1321,7 +1469,8 @@ int noalloc_scratch(void **ptr) {
 
 CellsDev cells_dev(const md_cells *c) {
   CellsDev d;
-  d.cell_start = c->start;
+  d.cell_start = c->sub ? c->cstart : c->start;
+  d.sub_start = c->sub ? c->start : nullptr;
   d.perm = c->perm;
   d.scomp = c->scomp;
   d.sx = c->sx, d.sy = c->sy, d.sz = c->sz;
@@ -1367,19 +1516,24 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
       else
         m->lds_limit = 64 * 1024;
     }
-    if (m->lj1_static_lds[f32] < 0) {
+    const bool sub = c->sub;
+    const void *kf = sub ? (f32 ? (const void *)k_pair_lj<float, true> : (const void *)k_pair_lj<double, true>)
+                         : (f32 ? (const void *)k_pair_lj<float, false> : (const void *)k_pair_lj<double, false>);
+    const int kv = (int)f32 + 2 * (int)sub;
+    if (m->lj1_static_lds[kv] < 0) {
       hipFuncAttributes fa{};
-      const void *kf = f32 ? (const void *)k_pair_lj<float> : (const void *)k_pair_lj<double>;
-      m->lj1_static_lds[f32] = hipFuncGetAttributes(&fa, kf) == hipSuccess ? (int)fa.sharedSizeBytes : 4096;
+      m->lj1_static_lds[kv] = hipFuncGetAttributes(&fa, kf) == hipSuccess ? (int)fa.sharedSizeBytes : 4096;
     }
-    const size_t stat = (size_t)m->lj1_static_lds[f32];
+    const size_t stat = (size_t)m->lj1_static_lds[kv];
     while (stat + dyn_lds(cap, lcap) > (size_t)m->lds_limit && cap > 256) cap = std::max(256, cap - 64);
     while (stat + dyn_lds(cap, lcap) > (size_t)m->lds_limit && lcap > 16) lcap -= 4;
     const size_t lds = dyn_lds(cap, lcap);
     const int64_t nq = pair_blocks((int64_t)c->nc[0] * ((c->nc[1] + 1) / 2) * ((c->nc[2] + 1) / 2));
     *nblocks = nq;
-    if (f32) k_pair_lj<float><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap);
-    else k_pair_lj<double><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap);
+    if (sub && f32) k_pair_lj<float, true><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap);
+    else if (sub) k_pair_lj<double, true><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap);
+    else if (f32) k_pair_lj<float, false><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap);
+    else k_pair_lj<double, false><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap);
     return check_hip(hipGetLastError(), "k_pair_lj");
   }
   const Shape &S = m->shape;

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmdcell.so")
 
 MD_OK, MD_EINVAL, MD_EBOX, MD_ECOMP, MD_ENONFINITE, MD_EHIP, MD_ENOMEM, MD_EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
-MD_LJ_SHIFT, MD_CHECK, MD_HALF_SHELL = 0x1, 0x2, 0x4
+MD_LJ_SHIFT, MD_CHECK, MD_HALF_SHELL, MD_SUBCELLS = 0x1, 0x2, 0x4, 0x8
 MD_FP64, MD_FP32 = 0, 1
 # device status word bits (Model.status)
 MD_DEV_NONFINITE, MD_DEV_COMP, MD_DEV_QUAT, MD_DEV_CAPACITY, MD_DEV_RANGE = 0x1, 0x2, 0x4, 0x8, 0x10
@@ -46,7 +46,7 @@ class ComponentDesc(ctypes.Structure):
 class CellsInfo(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int64), ("ncell", ctypes.c_int64), ("nc", ctypes.c_int32 * 3),
                 ("box", ctypes.c_double * 3), ("cell_of", ctypes.c_void_p), ("cell_start", ctypes.c_void_p),
-                ("perm", ctypes.c_void_p)]
+                ("perm", ctypes.c_void_p), ("sub_start", ctypes.c_void_p)]
 
 
 _lib = None
@@ -181,14 +181,15 @@ def long_range_correction(model: dict, counts, box):
 class Model:
     """A molecule model (component site tables, mixing, cutoff, reaction field) on the device.
     Built from the model dictionaries of ``workloads``.  ``half_shell`` selects the half-shell
-    pair kernel for a single-site model (MD_HALF_SHELL)."""
+    pair kernel for a single-site model (MD_HALF_SHELL); ``subcells`` the half-edge cell order and
+    culling of the single-site kernel (MD_SUBCELLS)."""
 
-    def __init__(self, model: dict, check: bool = False, half_shell: bool = False):
+    def __init__(self, model: dict, check: bool = False, half_shell: bool = False, subcells: bool = False):
         comps = model["components"]
         nc = len(comps)
         descs, self._keep, xi, eta = _component_descs(model)
         flags = ((MD_LJ_SHIFT if model.get("lj_shift") else 0) | (MD_CHECK if check else 0) |
-                 (MD_HALF_SHELL if half_shell else 0))
+                 (MD_HALF_SHELL if half_shell else 0) | (MD_SUBCELLS if subcells else 0))
         h = ctypes.c_void_p()
         _check(lib().md_model_create(descs, nc, None if xi is None else xi.ctypes.data_as(_dp),
                                      None if eta is None else eta.ctypes.data_as(_dp), float(model["rc"]),
@@ -277,8 +278,8 @@ class Cells:
             pass
 
     def view(self):
-        """Device copies of cell_of [N], cell_start [ncell+1], perm [N] (int32 CUDA tensors), plus
-        the grid shape."""
+        """Device copies of cell_of [N], cell_start [ncell+1], perm [N] and, for half-edge cells,
+        sub_start [8 ncell + 1] (int32 CUDA tensors; None otherwise), plus the grid shape."""
         info = CellsInfo()
         _check(lib().md_cells_view(self.handle, ctypes.byref(info)))
         N, nc = int(info.N), int(info.ncell)
@@ -290,7 +291,8 @@ class Cells:
 
         return {"N": N, "ncell": nc, "nc": tuple(info.nc), "box": tuple(info.box),
                 "cell_of": copy(info.cell_of, N), "cell_start": copy(info.cell_start, nc + 1),
-                "perm": copy(info.perm, N)}
+                "perm": copy(info.perm, N),
+                "sub_start": copy(info.sub_start, 8 * nc + 1) if info.sub_start else None}
 
 
 _hiprt = None

@@ -9,12 +9,13 @@ def dev(a, dtype=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
 
 
-def run_forces(md, cfg, precision="fp64", pos=None, quat=None, comp=None, model=None, check=False, half_shell=False):
+def run_forces(md, cfg, precision="fp64", pos=None, quat=None, comp=None, model=None, check=False, half_shell=False,
+               subcells=False):
     """Build cells and evaluate forces; returns (numpy dict, Model, Cells)."""
     pos = cfg["pos"] if pos is None else pos
     quat = cfg["quat"] if quat is None else quat
     comp = cfg["comp"] if comp is None else comp
-    m = md.Model(cfg["model"] if model is None else model, check=check, half_shell=half_shell)
+    m = md.Model(cfg["model"] if model is None else model, check=check, half_shell=half_shell, subcells=subcells)
     cells = md.Cells()
     ncomp = len((cfg["model"] if model is None else model)["components"])
     md.build_cells(m, cells, dev(pos), dev(quat), dev(comp, torch.int32) if ncomp > 1 else None, cfg["box"])

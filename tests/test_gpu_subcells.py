@@ -1,0 +1,172 @@
+"""Half-edge (r_c/2) cells on the GPU (Sec. 3, the r_c/2 cell variant), against the oracle.
+
+With MD_SUBCELLS the build sorts each cell's molecules by half-edge cell (then by original index)
+and the single-site kernel skips the far z-half of the cell layers above and below each
+molecule's own z-half.  Bars: cell ids, half-cell starts, the permutation, per-molecule partner
+counts and the pair count bit for bit (the pair set must not change); FP64 forces within 1e-11
+relative RMS and energies within 1e-12 relative; FP32 within the stated targets (force 1e-5
+relative RMS, energy 1e-9 relative), each with the per-molecule bound of ``assert_close``."""
+import numpy as np
+import pytest
+
+from tests._gpu import assert_close, dev, elem_err, rel_rms, run_forces
+from paper_1408_4599_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def md():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1408_4599_amd import md as _md
+    _md.lib()
+    return _md
+
+
+def _cfg(name):
+    if name == "gas_ragged":
+        return W.random_gas(1000, [9.1, 11.7, 14.2], W.lj_model(2.5), seed=7, dmin=0.75)
+    if name == "outside_box":
+        c = W.random_gas(1000, [10.0, 12.5, 15.0], W.lj_model(2.5), seed=9, dmin=0.75)
+        c["pos"] = c["pos"] * 3.0 - 7.0
+        return c
+    if name == "one_cell":  # 200 molecules in one cell: the chunked path for that home cell
+        rng = W.rng_for(43)
+        c = W.random_gas(10, [8.0, 8.0, 8.0], W.lj_model(2.5, shift=False), seed=41)
+        g = np.stack(np.meshgrid(*[np.arange(6)] * 3, indexing="ij"), -1).reshape(-1, 3)[:200]
+        c["pos"] = 0.2 + 0.45 * g + rng.uniform(-0.02, 0.02, size=(200, 3))
+        c["comp"] = np.zeros(200, dtype=np.int32)
+        return c
+    if name == "dense_lj":  # ~40 molecules per cell: tiles beyond the LDS tile take the window
+        return W.random_gas(2600, [12.0, 12.0, 12.0], W.lj_model(2.5), seed=33, dmin=0.7)
+    if name == "faces":  # many z and y coordinates on, or one rounding off, a half-cell face
+        c = W.random_gas(1500, [11.0, 12.0, 13.0], W.lj_model(2.5), seed=51, dmin=0.6)
+        box = np.asarray(c["box"])
+        hh = box / (2 * np.floor(box / 2.5))
+        rng = W.rng_for(52)
+        pos = c["pos"].copy()
+        for k in (1, 2):
+            sel = rng.uniform(size=len(pos)) < 0.4
+            pos[sel, k] = np.round(pos[sel, k] / hh[k]) * hh[k] * (1 + rng.choice([-2e-16, 0.0, 2e-16], size=sel.sum()))
+        # drop molecules that snapping brought closer than 0.6 to an earlier one
+        d = pos[:, None, :] - pos[None, :, :]
+        d -= box * np.round(d / box)
+        close = np.tril((d * d).sum(-1) < 0.36, -1).any(1)
+        c["pos"] = np.ascontiguousarray(pos[~close])
+        c["comp"] = np.zeros(len(c["pos"]), dtype=np.int32)
+        return c
+    return W.make(name)
+
+
+CASES = ["c1_ljts_4000", "c3_small", "gas_ragged", "outside_box", "one_cell", "dense_lj", "faces"]
+
+
+def _check_cells(v, oracle, pos, box, rc):
+    order, key = oracle.subcell_order(pos, box, rc)
+    cell_of, _, ncell = oracle.bin_cells(pos, box, rc)
+    assert v["ncell"] == ncell
+    np.testing.assert_array_equal(v["cell_of"].cpu().numpy(), cell_of)
+    np.testing.assert_array_equal(v["perm"].cpu().numpy(), order)
+    sub = v["sub_start"].cpu().numpy()
+    np.testing.assert_array_equal(np.diff(sub), np.bincount(key, minlength=8 * ncell))
+    assert sub[0] == 0 and sub[-1] == len(pos)
+    np.testing.assert_array_equal(v["cell_start"].cpu().numpy(), sub[::8])
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_subcell_order_bit_exact(md, oracle, name):
+    cfg = _cfg(name)
+    _, m, cells = run_forces(md, cfg, "fp64", subcells=True)
+    _check_cells(cells.view(), oracle, cfg["pos"], cfg["box"], cfg["model"]["rc"])
+
+
+def test_subcell_rebuild_in_previous_order(md, oracle):
+    """A rebuild of the same cells object visits molecules in the previous sorted order; the
+    half-cell order must still be the oracle's."""
+    cfg = W.make("c1_ljts_4000")
+    moved = cfg["pos"] + W.rng_for(78).uniform(-0.6, 0.6, size=cfg["pos"].shape)
+    m = md.Model(cfg["model"], subcells=True)
+    cells = md.Cells()
+    md.build_cells(m, cells, dev(cfg["pos"]), None, None, cfg["box"])
+    md.build_cells(m, cells, dev(moved), None, None, cfg["box"])
+    _check_cells(cells.view(), oracle, moved, cfg["box"], cfg["model"]["rc"])
+
+
+def test_one_cells_object_switches_models(md, oracle):
+    """One cells object built alternately for a model with and one without half-edge cells: each
+    build carries its own order."""
+    cfg = W.make("c1_ljts_4000")
+    a, b = md.Model(cfg["model"], subcells=True), md.Model(cfg["model"])
+    cells = md.Cells()
+    for m, sub in ((a, True), (b, False), (a, True)):
+        md.build_cells(m, cells, dev(cfg["pos"]), None, None, cfg["box"])
+        v = cells.view()
+        if sub:
+            _check_cells(v, oracle, cfg["pos"], cfg["box"], cfg["model"]["rc"])
+        else:
+            assert v["sub_start"] is None
+            ref_cell, _, _ = oracle.bin_cells(cfg["pos"], cfg["box"], cfg["model"]["rc"])
+            np.testing.assert_array_equal(v["perm"].cpu().numpy(), np.lexsort((np.arange(len(ref_cell)), ref_cell)))
+        out = md.forces(m, cells, "fp64")
+        assert int(out["npairs"][0]) > 0
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_subcell_forces_fp64_match_oracle(md, oracle, name):
+    cfg = _cfg(name)
+    ref = oracle.rows(cfg["model"], cfg["pos"], None, None, cfg["box"])
+    got, _, _ = run_forces(md, cfg, "fp64", subcells=True)
+    np.testing.assert_array_equal(got["nnb"], ref["nnb"])
+    assert got["npairs"] == ref["nnb"].sum() // 2
+    assert_close(got["force"], ref["F"], 1e-11, "force")
+    assert got["U"] == pytest.approx(ref["u"].sum(), rel=1e-12)
+    assert got["W"] == pytest.approx(ref["w"].sum(), rel=1e-12)
+    np.testing.assert_allclose(got["Wd"], ref["wd"].sum(0), rtol=1e-12)
+    assert_close(got["u_mol"], ref["u"], 1e-11, "u_mol")
+    assert_close(got["w_mol"], ref["w"], 1e-11, "w_mol")
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_subcell_forces_fp32_within_stated_error(md, oracle, name):
+    cfg = _cfg(name)
+    ref = oracle.rows(cfg["model"], cfg["pos"], None, None, cfg["box"])
+    got, _, _ = run_forces(md, cfg, "fp32", subcells=True)
+    np.testing.assert_array_equal(got["nnb"], ref["nnb"])
+    eF, mF = rel_rms(got["force"], ref["F"]), elem_err(got["force"], ref["F"])
+    eU = abs(got["U"] - ref["u"].sum()) / abs(ref["u"].sum())
+    print(f"{name}: half-edge cells fp32 eps_F {eF:.2e} (max per molecule {mF:.2e}) eps_U {eU:.2e}", flush=True)
+    assert eF < 1e-5 and mF < 1e-4
+    assert eU < 1e-9
+    assert_close(got["u_mol"], ref["u"], 1e-6, "u_mol")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_subcells_equal_default_kernel(md, precision):
+    """Same configuration with and without half-edge cells: identical partner counts, forces equal
+    to rounding (the summation order of a molecule's partners differs)."""
+    cfg = W.make("c3_small")
+    a, _, _ = run_forces(md, cfg, precision)
+    b, _, _ = run_forces(md, cfg, precision, subcells=True)
+    np.testing.assert_array_equal(a["nnb"], b["nnb"])
+    bar = 1e-13 if precision == "fp64" else 1e-6
+    assert_close(b["force"], a["force"], bar, "force")
+    assert b["U"] == pytest.approx(a["U"], rel=1e-12 if precision == "fp64" else 1e-10)
+
+
+def test_subcells_step_matches_default(md):
+    """md_step with half-edge cells (rebuilt every step) follows the default kernel's trajectory to
+    rounding over 20 FP64 steps."""
+    import torch
+    cfg = W.make("c1_ljts_4000")
+    out = []
+    for sub in (False, True):
+        m = md.Model(cfg["model"], subcells=sub)
+        cells = md.Cells()
+        pos, vel = dev(cfg["pos"]), dev(cfg["vel"])
+        en = md.step(m, cells, pos, vel, None, None, None, cfg["box"], cfg["dt"], 20, "fp64")
+        torch.cuda.synchronize()
+        out.append((pos.cpu().numpy(), en.cpu().numpy()))
+    np.testing.assert_allclose(out[1][0], out[0][0], rtol=0, atol=1e-10)
+    np.testing.assert_allclose(out[1][1], out[0][1], rtol=1e-10)
