@@ -170,3 +170,123 @@ def test_subcells_step_matches_default(md):
         out.append((pos.cpu().numpy(), en.cpu().numpy()))
     np.testing.assert_allclose(out[1][0], out[0][0], rtol=0, atol=1e-10)
     np.testing.assert_allclose(out[1][1], out[0][1], rtol=1e-10)
+
+
+def _min_image(d, box):
+    return d - box * np.round(d / box)
+
+
+@pytest.mark.parametrize("prec,nsteps", [("fp64", 30), ("fp32", 10)])
+def test_subcell_step_matches_oracle_trajectory(md, oracle, prec, nsteps):
+    """md_step with half-edge cells (the benchmarked path) against the oracle's integrator on C1:
+    FP64 at the default kernel's FP64 bars (positions 1e-9, velocities 1e-6, energies 1e-9), FP32
+    at those of its FP32 trajectory test (positions 1e-7 absolute, velocities 1e-5, per-step U
+    1e-9, K 1e-8, W 1e-6)."""
+    import torch
+    cfg = W.make("c1_ljts_4000")
+    p_ref, v_ref, _, _, e_ref = oracle.step(cfg["model"], cfg["pos"], cfg["vel"], None, None, cfg["comp"],
+                                            cfg["box"], cfg["dt"], nsteps)
+    m = md.Model(cfg["model"], subcells=True)
+    cells = md.Cells()
+    pos, vel = dev(cfg["pos"]), dev(cfg["vel"])
+    en = md.step(m, cells, pos, vel, None, None, None, cfg["box"], cfg["dt"], nsteps, prec)
+    torch.cuda.synchronize()
+    p, v, e = pos.cpu().numpy(), vel.cpu().numpy(), en.cpu().numpy()
+    dp = np.abs(_min_image(p - p_ref, cfg["box"])).max()
+    dv = np.abs(v - v_ref).max()
+    rel = np.abs(e - e_ref) / np.abs(e_ref).max(axis=0).clip(1e-300)
+    print(f"{prec}: max |dpos| {dp:.2e} |dvel| {dv:.2e} U {rel[:, 0].max():.2e} K {rel[:, 1].max():.2e} "
+          f"W {rel[:, 3].max():.2e}", flush=True)
+    if prec == "fp64":  # the default kernel's FP64 trajectory bars
+        assert dp < 1e-9 and dv < 1e-6 and rel.max() < 1e-9
+    else:
+        assert dp < 1e-7 and dv < 1e-5
+        assert rel[:, 0].max() < 1e-9 and rel[:, 1].max() < 1e-8 and rel[:, 3].max() < 1e-6
+
+
+def test_subcell_nonfinite_molecules_take_no_part(md, oracle):
+    """Non-finite molecules go to half-cell 0 of cell (index mod ncell), take part in no pair, and
+    the others match the oracle for the system without them."""
+    cfg = W.make("c1_ljts_4000")
+    pos = cfg["pos"].copy()
+    N = len(pos)
+    bad = np.sort(np.random.default_rng(15).choice(N, N // 10, replace=False))
+    pos[bad[::2], 0] = np.nan
+    pos[bad[1::2], 2] = -np.inf
+    keep = np.setdiff1d(np.arange(N), bad)
+    ref = oracle.rows(cfg["model"], pos[keep], None, None, cfg["box"])
+    for prec, bar in (("fp64", 1e-11), ("fp32", 1e-5)):
+        got, m, cells = run_forces(md, cfg, prec, pos=pos, subcells=True)
+        assert m.status() & md.MD_DEV_NONFINITE
+        assert np.all(got["nnb"][bad] == 0) and np.all(got["force"][bad] == 0)
+        np.testing.assert_array_equal(got["nnb"][keep], ref["nnb"])
+        assert_close(got["force"][keep], ref["F"], bar, f"{prec} force")
+    v = cells.view()
+    ncell = v["ncell"]
+    np.testing.assert_array_equal(v["cell_of"].cpu().numpy()[bad], bad % ncell)
+    sub = v["sub_start"].cpu().numpy()
+    perm = v["perm"].cpu().numpy()
+    slot = np.empty(N, dtype=np.int64)
+    slot[perm] = np.arange(N)
+    # each non-finite molecule sits in half-cell 0 (octant 0) of its cell
+    for i in bad[:20]:
+        c = i % ncell
+        assert sub[8 * c] <= slot[i] < sub[8 * c + 1]
+
+
+def test_subcell_tiny_systems(md, oracle):
+    """N = 2 in a large box (almost every cell empty) and N = 1 (no pairs)."""
+    mdl = W.lj_model(2.5, shift=False)
+    cfg = {"model": mdl, "pos": np.array([[1.0, 1.0, 1.0], [2.2, 1.3, 0.9]]), "quat": None,
+           "comp": np.zeros(2, np.int32), "box": np.array([12.0, 13.0, 14.0])}
+    got, _, _ = run_forces(md, cfg, "fp64", subcells=True)
+    ref = oracle.forces(mdl, cfg["pos"], None, None, cfg["box"])
+    assert got["npairs"] == 1
+    np.testing.assert_allclose(got["force"], ref["F"], rtol=1e-13)
+    cfg["pos"], cfg["comp"] = cfg["pos"][:1], cfg["comp"][:1]
+    got, _, _ = run_forces(md, cfg, "fp32", subcells=True)
+    assert got["npairs"] == 0 and np.all(got["force"] == 0) and got["U"] == 0.0
+
+
+@pytest.mark.parametrize("box", [[7.6, 8.0, 9.9], [7.6, 12.6, 7.7]])
+def test_subcell_three_cell_grids(md, oracle, box):
+    """Three cells along some axes: the tile of a block holds the same cell twice (two images),
+    and the half-layer walk wraps on both sides."""
+    cfg = W.random_gas(int(0.7 * np.prod(box)), box, W.lj_model(2.5), seed=61, dmin=0.8)
+    ref = oracle.rows(cfg["model"], cfg["pos"], None, None, cfg["box"])
+    for prec, bar in (("fp64", 1e-11), ("fp32", 1e-5)):
+        got, _, cells = run_forces(md, cfg, prec, subcells=True)
+        np.testing.assert_array_equal(got["nnb"], ref["nnb"])
+        assert_close(got["force"], ref["F"], bar, f"{prec} force")
+        assert got["U"] == pytest.approx(ref["u"].sum(), rel=1e-12 if prec == "fp64" else 1e-9)
+    _check_cells(cells.view(), oracle, cfg["pos"], cfg["box"], 2.5)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_subcell_adjoint_and_noalloc_equal_default(md, prec):
+    """The adjoint and the allocation-free entry point on cells built with half-edge cells: the
+    adjoint equals the default one to rounding, md_forces_noalloc equals md_forces bit for bit."""
+    import torch
+    cfg = W.make("c1_ljts_4000")
+    out = []
+    for sub in (False, True):
+        m = md.Model(cfg["model"], subcells=sub)
+        cells = md.Cells()
+        md.build_cells(m, cells, dev(cfg["pos"]), None, None, cfg["box"])
+        g = md.forces_adjoint(m, cells, prec, 1.0, want_quat=False)
+        torch.cuda.synchronize()
+        out.append((g["dpos"].cpu().numpy(), g["dparams"].cpu().numpy()))
+        if sub:
+            N = len(cfg["pos"])
+            mk = lambda v: {"force": torch.full((N, 3), v, dtype=torch.float64, device="cuda"),
+                            "uw": torch.full((5,), v, dtype=torch.float64, device="cuda"),
+                            "npairs": torch.full((1,), -3, dtype=torch.int64, device="cuda")}
+            a, b = mk(1.0), mk(-2.0)
+            md.forces_into(m, cells, prec, a)
+            md.forces_into_noalloc(m, cells, prec, b)
+            torch.cuda.synchronize()
+            for k in a:
+                np.testing.assert_array_equal(b[k].cpu().numpy(), a[k].cpu().numpy())
+    bar = 1e-12 if prec == "fp64" else 1e-6
+    assert_close(out[1][0], out[0][0], bar, "dpos")
+    np.testing.assert_allclose(out[1][1], out[0][1], rtol=bar, atol=bar * np.abs(out[0][1]).max())
