@@ -366,6 +366,37 @@ def main():
     f32_wall, f32_pair = time_forces("fp32", args.force_evals)
     f64_wall, f64_pair = (None, None) if args.no_fp64 else time_forces("fp64", args.force_evals)
 
+    # ---- the same evaluation with plain cells (27-cell walk), for the half-edge cells' gain ----
+    plain = None
+    if subcells and not args.quick:
+        pm, pc = md.Model(cfg["model"]), md.Cells()
+        md.build_cells(pm, pc, pos0, quat0, comp_t, cfg["box"])
+        buf = {"force": torch.empty((N, 3), dtype=torch.float64, device="cuda"),
+               "uw": torch.empty(5, dtype=torch.float64, device="cuda"),
+               "npairs": torch.empty(1, dtype=torch.int64, device="cuda")}
+        plain = {}
+        for prec in ("fp32", "fp64"):
+            for _ in range(3):
+                md.forces_into(pm, pc, prec, buf)
+            torch.cuda.synchronize()
+            pm.profile(True)
+            for _ in range(args.force_evals):
+                md.forces_into(pm, pc, prec, buf)
+            torch.cuda.synchronize()
+            ms, k = pm.profile_read("pair")
+            pm.profile(False)
+            plain[prec + "_pair_kernel_ms"] = ms / k
+        pm.profile(True)
+        for _ in range(max(5, args.force_evals // 5)):
+            md.build_cells(pm, pc, pos0, quat0, comp_t, cfg["box"])
+        torch.cuda.synchronize()
+        ms, k = pm.profile_read("build")
+        pm.profile(False)
+        plain["ms_per_build"] = ms / k
+        plain["walk_distance_tests"] = walk_tests(pc.view())["full_27_cells"]
+        pc.close()
+        pm.close()
+
     # ---- full steps ----
     def run_steps(prec, nsteps=None):
         nsteps = args.steps if nsteps is None else nsteps
@@ -454,6 +485,12 @@ def main():
                      "executed_fp32_frac": None if ex32 is None else ex32 / f32_pair / PEAK_FP32,
                      "executed_fp64_flop_per_launch": ex64,
                      "executed_fp64_frac": None if ex64 is None else ex64 / f32_pair / PEAK_FP64},
+        "plain_cells": None if plain is None else {
+            **plain, "fp32_pair_kernel_ms_half_edge": 1e3 * f32_pair,
+            "fp64_pair_kernel_ms_half_edge": None if f64_pair is None else 1e3 * f64_pair,
+            "ms_per_build_half_edge": 1e3 * build_s,
+            "note": "the same configuration with plain cells (MD_SUBCELLS off): pair kernel (HIP events), "
+                    "build and the 27-cell walk's distance tests, beside the half-edge figures"},
         "cell_sort_roofline": {"bound": "hbm", "achieved": build_bytes / build_s / 1e9, "peak": PEAK_HBM / 1e9,
                                "unit": "GB/s", "frac": build_bytes / build_s / PEAK_HBM,
                                "ms_per_build": 1e3 * build_s, "algorithmic_bytes_per_build": build_bytes,
