@@ -159,6 +159,7 @@ struct md_model {
   hipStream_t side = nullptr;
   hipEvent_t ev_leap[2] = {nullptr, nullptr}, ev_red[2] = {nullptr, nullptr};
   int lds_limit = 0;            // LDS bytes per block on the model's device (queried at first use)
+  int lds_per_cu = 0;           // LDS bytes per CU (queried at first use)
   int lj1_static_lds[4] = {-1, -1, -1, -1};  // static LDS of the single-site pair kernel (FP64, FP32;
                                              // then with half-edge cells)
   // profiling

@@ -255,6 +255,59 @@ __device__ __forceinline__ void lj_hit(LJFlush<R> &a, double dx, double dy, doub
   a.n += 1;
 }
 
+// Two listed partners at once (two independent dependency chains for the latency-bound flush),
+// added to the sums in the order hit 0, hit 1, so the sums equal those of two lj_hit calls bit for
+// bit.  FP32 path: a partner outside the exact cutoff (listed by the guard band) adds nothing.
+template <typename R>
+__device__ __forceinline__ void lj_hit2(LJFlush<R> &a, double dx0, double dy0, double dz0, double dx1, double dy1,
+                                        double dz1, const LJK &k) {
+  const double r20 = fma(dz0, dz0, fma(dy0, dy0, dx0 * dx0));
+  const double r21 = fma(dz1, dz1, fma(dy1, dy1, dx1 * dx1));
+  if constexpr (std::is_same<R, float>::value) {
+    const bool in0 = r20 < k.rc2, in1 = r21 < k.rc2;
+    const float y0 = __builtin_amdgcn_rcpf((float)r20), y1 = __builtin_amdgcn_rcpf((float)r21);
+    const double yd0 = fma((double)y0, fma(-r20, (double)y0, 1.0), (double)y0);
+    const double yd1 = fma((double)y1, fma(-r21, (double)y1, 1.0), (double)y1);
+    const double s20 = k.sig2 * yd0, s60 = s20 * s20 * s20;
+    const double s21 = k.sig2 * yd1, s61 = s21 * s21 * s21;
+    const float t20 = k.sig2f * y0, t60 = t20 * t20 * t20;
+    const float t21 = k.sig2f * y1, t61 = t21 * t21 * t21;
+    const float fs0 = (k.eps24f * y0) * (t60 * fmaf(2.0f, t60, -1.0f));
+    const float fs1 = (k.eps24f * y1) * (t61 * fmaf(2.0f, t61, -1.0f));
+    const float ex0 = (float)dx0, ey0 = (float)dy0, ez0 = (float)dz0;
+    const float ex1 = (float)dx1, ey1 = (float)dy1, ez1 = (float)dz1;
+    const float gx0 = fs0 * ex0, gy0 = fs0 * ey0, gz0 = fs0 * ez0;
+    const float gx1 = fs1 * ex1, gy1 = fs1 * ey1, gz1 = fs1 * ez1;
+    if (in0) {
+      a.u = fma(k.eps4 * s60, s60 - 1.0, a.u);
+      a.fx += gx0, a.fy += gy0, a.fz += gz0;
+      a.wx = fmaf(gx0, ex0, a.wx), a.wy = fmaf(gy0, ey0, a.wy), a.wz = fmaf(gz0, ez0, a.wz);
+      a.n += 1;
+    }
+    if (in1) {
+      a.u = fma(k.eps4 * s61, s61 - 1.0, a.u);
+      a.fx += gx1, a.fy += gy1, a.fz += gz1;
+      a.wx = fmaf(gx1, ex1, a.wx), a.wy = fmaf(gy1, ey1, a.wy), a.wz = fmaf(gz1, ez1, a.wz);
+      a.n += 1;
+    }
+  } else {
+    const double y0 = rcp_nr<double>(r20), y1 = rcp_nr<double>(r21);
+    const double s20 = k.sig2 * y0, s60 = s20 * s20 * s20;
+    const double s21 = k.sig2 * y1, s61 = s21 * s21 * s21;
+    const double fs0 = (k.eps24 * y0) * (s60 * fma(2.0, s60, -1.0));
+    const double fs1 = (k.eps24 * y1) * (s61 * fma(2.0, s61, -1.0));
+    const double gx0 = fs0 * dx0, gy0 = fs0 * dy0, gz0 = fs0 * dz0;
+    const double gx1 = fs1 * dx1, gy1 = fs1 * dy1, gz1 = fs1 * dz1;
+    a.u = fma(k.eps4 * s60, s60 - 1.0, a.u);
+    a.fx += gx0, a.fy += gy0, a.fz += gz0;
+    a.wx = fma(gx0, dx0, a.wx), a.wy = fma(gy0, dy0, a.wy), a.wz = fma(gz0, dz0, a.wz);
+    a.u = fma(k.eps4 * s61, s61 - 1.0, a.u);
+    a.fx += gx1, a.fy += gy1, a.fz += gz1;
+    a.wx = fma(gx1, dx1, a.wx), a.wy = fma(gy1, dy1, a.wy), a.wz = fma(gz1, dz1, a.wz);
+    a.n += 2;
+  }
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -267,8 +320,12 @@ __device__ __forceinline__ void wave_sync_lds() {
 // (tile z half-layers 2 hz .. 2 hz + 5 surround home cell hz): the sixth lies more than one cell
 // edge (>= r_c) away along z, so none of its pairs is inside the cutoff.  Each lane's range starts
 // at its molecule's half; the runs all lanes fill are walked unchecked, the rest bounds-checked.
-template <typename R, bool SUB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_pair_lj(CellsDev c, LJK k, PairOut o, int cap, int lcap) {
+// WPE: wavefronts per SIMD the register allocation must allow.  5 where the LDS of a block leaves
+// room for 5 blocks per CU (sparse tiles): the flush then takes one hit per iteration, since two
+// spill at that register count; 4 where LDS holds 4 blocks (dense tiles), with two hits per
+// iteration of the flush.
+template <typename R, bool SUB, int WPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_pair_lj(CellsDev c, LJK k, PairOut o, int cap, int lcap) {
   constexpr bool F32 = std::is_same<R, float>::value;
   // staged groups: tile cells (3 x 4 x 4, cell u = ux + 3 uy + 12 uz), or with SUB the cell halves
   // in the order g = (uy * 8 + z half-layer) * 3 + ux
@@ -492,20 +549,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         auto flush = [&]() {
           const int cnt = (int)(lp - mylist) >> 6;
           if (act) {
+            // WPE 4: two hits per iteration (independent chains), the odd one after
+            auto run = [&](auto &acc) {
+              using A = typename std::remove_reference<decltype(acc)>::type;
+              using RA = decltype(A::fx);
+              int q = 0;
+              if constexpr (WPE <= 4)
+                for (; q + 2 <= cnt; q += 2) {
+                  const int e0 = mylist[64 * q], e1 = mylist[64 * q + 64];
+                  lj_hit2<RA>(acc, xi - l64[3 * e0], yi - l64[3 * e0 + 1], zi - l64[3 * e0 + 2], xi - l64[3 * e1],
+                              yi - l64[3 * e1 + 1], zi - l64[3 * e1 + 2], k);
+                }
+              for (; q < cnt; ++q) {
+                const int e = mylist[64 * q];
+                lj_hit<RA>(acc, xi - l64[3 * e], yi - l64[3 * e + 1], zi - l64[3 * e + 2], k);
+              }
+            };
             if constexpr (F32) {
               LJFlush<float> a;
-              for (int q = 0; q < cnt; ++q) {
-                const int e = mylist[64 * q];
-                lj_hit<float>(a, xi - l64[3 * e], yi - l64[3 * e + 1], zi - l64[3 * e + 2], k);
-              }
+              run(a);
               sfx += (double)a.fx, sfy += (double)a.fy, sfz += (double)a.fz;
               swx += (double)a.wx, swy += (double)a.wy, swz += (double)a.wz;
               su += a.u, sn += a.n;
             } else {
-              for (int q = 0; q < cnt; ++q) {
-                const int e = mylist[64 * q];
-                lj_hit<double>(a64, xi - l64[3 * e], yi - l64[3 * e + 1], zi - l64[3 * e + 2], k);
-              }
+              run(a64);
             }
           }
           lp = mylist;
@@ -1517,8 +1584,9 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
         m->lds_limit = 64 * 1024;
     }
     const bool sub = c->sub;
-    const void *kf = sub ? (f32 ? (const void *)k_pair_lj<float, true> : (const void *)k_pair_lj<double, true>)
-                         : (f32 ? (const void *)k_pair_lj<float, false> : (const void *)k_pair_lj<double, false>);
+    // the static LDS of the instances (the same for both WPE variants)
+    const void *kf = sub ? (f32 ? (const void *)k_pair_lj<float, true, 4> : (const void *)k_pair_lj<double, true, 4>)
+                         : (f32 ? (const void *)k_pair_lj<float, false, 4> : (const void *)k_pair_lj<double, false, 4>);
     const int kv = (int)f32 + 2 * (int)sub;
     if (m->lj1_static_lds[kv] < 0) {
       hipFuncAttributes fa{};
@@ -1530,10 +1598,24 @@ int launch_pair(md_model *m, const md_cells *c, int precision, const PairOut &o,
     const size_t lds = dyn_lds(cap, lcap);
     const int64_t nq = pair_blocks((int64_t)c->nc[0] * ((c->nc[1] + 1) / 2) * ((c->nc[2] + 1) / 2));
     *nblocks = nq;
-    if (sub && f32) k_pair_lj<float, true><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap);
-    else if (sub) k_pair_lj<double, true><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap);
-    else if (f32) k_pair_lj<float, false><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap);
-    else k_pair_lj<double, false><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap);
+    // blocks per CU that the LDS allows decides the register budget of the instance
+    if (!m->lds_per_cu) {
+      int dev = 0, v = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess && v > 0)
+        m->lds_per_cu = v;
+      else
+        m->lds_per_cu = 160 * 1024;
+    }
+    const bool w5 = (size_t)m->lds_per_cu / (stat + lds) >= 5;
+#define MD_LJ_LAUNCH(RR, SS)                                                                 \
+  (w5 ? k_pair_lj<RR, SS, 5><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap)             \
+      : k_pair_lj<RR, SS, 4><<<(unsigned)nq, 256, lds, s>>>(cd, k, o, cap, lcap))
+    if (sub && f32) MD_LJ_LAUNCH(float, true);
+    else if (sub) MD_LJ_LAUNCH(double, true);
+    else if (f32) MD_LJ_LAUNCH(float, false);
+    else MD_LJ_LAUNCH(double, false);
+#undef MD_LJ_LAUNCH
     return check_hip(hipGetLastError(), "k_pair_lj");
   }
   const Shape &S = m->shape;
