@@ -473,7 +473,9 @@ def main():
         "roofline": {"bound": "alu", "achieved": W_alg / f32_pair / 1e12, "peak": PEAK_FP32 / 1e12,
                      "unit": "TFLOP/s", "frac": W_alg / f32_pair / PEAK_FP32,
                      "traffic": traffic,
-                     "kernel": ("k_pair_lj<float, true>" if subcells else "k_pair_lj<float, false>")
+                     # the last template argument (waves per SIMD: 4, or 5 where the LDS of a block
+                     # leaves room for 5 blocks per CU) is chosen at launch; C2 takes 4
+                     "kernel": ("k_pair_lj<float, true, 4|5>" if subcells else "k_pair_lj<float, false, 4|5>")
                                if model.single_site else "k_pair_ms<float>",
                      "algorithmic_flop_per_launch": W_alg,
                      "accounting": f"{DIST_TEST_FLOP} FLOP per half-shell distance test (D) + "
