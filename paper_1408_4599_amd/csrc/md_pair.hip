@@ -208,6 +208,7 @@ __device__ __forceinline__ void write_partial_block(double *partial, double acc5
 constexpr int QCELLS = 48;  // 3 x 4 x 4 staged cells
 constexpr int NSMAX = 8;
 constexpr int SLACK = 32;  // spare tile entries read (never counted) past the end of a walk
+constexpr int FLUSH_H = 3;  // listed partners per flush iteration in the 4-wave instances
 constexpr unsigned short LIST_END = 0xFFFF;  // end marker of a hit list (slots stay below 4096)
 typedef float f4v __attribute__((ext_vector_type(4)));
 
@@ -255,56 +256,56 @@ __device__ __forceinline__ void lj_hit(LJFlush<R> &a, double dx, double dy, doub
   a.n += 1;
 }
 
-// Two listed partners at once (two independent dependency chains for the latency-bound flush),
-// added to the sums in the order hit 0, hit 1, so the sums equal those of two lj_hit calls bit for
-// bit.  FP32 path: a partner outside the exact cutoff (listed by the guard band) adds nothing.
-template <typename R>
-__device__ __forceinline__ void lj_hit2(LJFlush<R> &a, double dx0, double dy0, double dz0, double dx1, double dy1,
-                                        double dz1, const LJK &k) {
-  const double r20 = fma(dz0, dz0, fma(dy0, dy0, dx0 * dx0));
-  const double r21 = fma(dz1, dz1, fma(dy1, dy1, dx1 * dx1));
+// H listed partners at once (H independent dependency chains for the latency-bound flush), added
+// to the sums in listing order, so the sums equal those of H lj_hit calls bit for bit.  FP32 path:
+// a partner outside the exact cutoff (listed by the guard band) adds nothing.
+template <typename R, int H>
+__device__ __forceinline__ void lj_hitn(LJFlush<R> &a, const double (&dx)[H], const double (&dy)[H],
+                                        const double (&dz)[H], const LJK &k) {
+  double r2[H];
+#pragma unroll
+  for (int h = 0; h < H; ++h) r2[h] = fma(dz[h], dz[h], fma(dy[h], dy[h], dx[h] * dx[h]));
   if constexpr (std::is_same<R, float>::value) {
-    const bool in0 = r20 < k.rc2, in1 = r21 < k.rc2;
-    const float y0 = __builtin_amdgcn_rcpf((float)r20), y1 = __builtin_amdgcn_rcpf((float)r21);
-    const double yd0 = fma((double)y0, fma(-r20, (double)y0, 1.0), (double)y0);
-    const double yd1 = fma((double)y1, fma(-r21, (double)y1, 1.0), (double)y1);
-    const double s20 = k.sig2 * yd0, s60 = s20 * s20 * s20;
-    const double s21 = k.sig2 * yd1, s61 = s21 * s21 * s21;
-    const float t20 = k.sig2f * y0, t60 = t20 * t20 * t20;
-    const float t21 = k.sig2f * y1, t61 = t21 * t21 * t21;
-    const float fs0 = (k.eps24f * y0) * (t60 * fmaf(2.0f, t60, -1.0f));
-    const float fs1 = (k.eps24f * y1) * (t61 * fmaf(2.0f, t61, -1.0f));
-    const float ex0 = (float)dx0, ey0 = (float)dy0, ez0 = (float)dz0;
-    const float ex1 = (float)dx1, ey1 = (float)dy1, ez1 = (float)dz1;
-    const float gx0 = fs0 * ex0, gy0 = fs0 * ey0, gz0 = fs0 * ez0;
-    const float gx1 = fs1 * ex1, gy1 = fs1 * ey1, gz1 = fs1 * ez1;
-    if (in0) {
-      a.u = fma(k.eps4 * s60, s60 - 1.0, a.u);
-      a.fx += gx0, a.fy += gy0, a.fz += gz0;
-      a.wx = fmaf(gx0, ex0, a.wx), a.wy = fmaf(gy0, ey0, a.wy), a.wz = fmaf(gz0, ez0, a.wz);
-      a.n += 1;
+    bool in[H];
+    double s6[H];
+    float gx[H], gy[H], gz[H], ex[H], ey[H], ez[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      in[h] = r2[h] < k.rc2;
+      const float y = __builtin_amdgcn_rcpf((float)r2[h]);
+      const double yd = fma((double)y, fma(-r2[h], (double)y, 1.0), (double)y);
+      const double s2 = k.sig2 * yd;
+      s6[h] = s2 * s2 * s2;
+      const float t2 = k.sig2f * y, t6 = t2 * t2 * t2;
+      const float fs = (k.eps24f * y) * (t6 * fmaf(2.0f, t6, -1.0f));
+      ex[h] = (float)dx[h], ey[h] = (float)dy[h], ez[h] = (float)dz[h];
+      gx[h] = fs * ex[h], gy[h] = fs * ey[h], gz[h] = fs * ez[h];
     }
-    if (in1) {
-      a.u = fma(k.eps4 * s61, s61 - 1.0, a.u);
-      a.fx += gx1, a.fy += gy1, a.fz += gz1;
-      a.wx = fmaf(gx1, ex1, a.wx), a.wy = fmaf(gy1, ey1, a.wy), a.wz = fmaf(gz1, ez1, a.wz);
-      a.n += 1;
-    }
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+      if (in[h]) {
+        a.u = fma(k.eps4 * s6[h], s6[h] - 1.0, a.u);
+        a.fx += gx[h], a.fy += gy[h], a.fz += gz[h];
+        a.wx = fmaf(gx[h], ex[h], a.wx), a.wy = fmaf(gy[h], ey[h], a.wy), a.wz = fmaf(gz[h], ez[h], a.wz);
+        a.n += 1;
+      }
   } else {
-    const double y0 = rcp_nr<double>(r20), y1 = rcp_nr<double>(r21);
-    const double s20 = k.sig2 * y0, s60 = s20 * s20 * s20;
-    const double s21 = k.sig2 * y1, s61 = s21 * s21 * s21;
-    const double fs0 = (k.eps24 * y0) * (s60 * fma(2.0, s60, -1.0));
-    const double fs1 = (k.eps24 * y1) * (s61 * fma(2.0, s61, -1.0));
-    const double gx0 = fs0 * dx0, gy0 = fs0 * dy0, gz0 = fs0 * dz0;
-    const double gx1 = fs1 * dx1, gy1 = fs1 * dy1, gz1 = fs1 * dz1;
-    a.u = fma(k.eps4 * s60, s60 - 1.0, a.u);
-    a.fx += gx0, a.fy += gy0, a.fz += gz0;
-    a.wx = fma(gx0, dx0, a.wx), a.wy = fma(gy0, dy0, a.wy), a.wz = fma(gz0, dz0, a.wz);
-    a.u = fma(k.eps4 * s61, s61 - 1.0, a.u);
-    a.fx += gx1, a.fy += gy1, a.fz += gz1;
-    a.wx = fma(gx1, dx1, a.wx), a.wy = fma(gy1, dy1, a.wy), a.wz = fma(gz1, dz1, a.wz);
-    a.n += 2;
+    double s6[H], gx[H], gy[H], gz[H];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const double y = rcp_nr<double>(r2[h]);
+      const double s2 = k.sig2 * y;
+      s6[h] = s2 * s2 * s2;
+      const double fs = (k.eps24 * y) * (s6[h] * fma(2.0, s6[h], -1.0));
+      gx[h] = fs * dx[h], gy[h] = fs * dy[h], gz[h] = fs * dz[h];
+    }
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      a.u = fma(k.eps4 * s6[h], s6[h] - 1.0, a.u);
+      a.fx += gx[h], a.fy += gy[h], a.fz += gz[h];
+      a.wx = fma(gx[h], dx[h], a.wx), a.wy = fma(gy[h], dy[h], a.wy), a.wz = fma(gz[h], dz[h], a.wz);
+    }
+    a.n += H;
   }
 }
 
@@ -321,8 +322,8 @@ __device__ __forceinline__ void wave_sync_lds() {
 // edge (>= r_c) away along z, so none of its pairs is inside the cutoff.  Each lane's range starts
 // at its molecule's half; the runs all lanes fill are walked unchecked, the rest bounds-checked.
 // WPE: wavefronts per SIMD the register allocation must allow.  5 where the LDS of a block leaves
-// room for 5 blocks per CU (sparse tiles): the flush then takes one hit per iteration, since two
-// spill at that register count; 4 where LDS holds 4 blocks (dense tiles), with two hits per
+// room for 5 blocks per CU (sparse tiles): the flush then takes one hit per iteration, since more
+// spill at that register count; 4 where LDS holds 4 blocks (dense tiles), with FLUSH_H hits per
 // iteration of the flush.
 template <typename R, bool SUB, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void k_pair_lj(CellsDev c, LJK k, PairOut o, int cap, int lcap) {
@@ -549,17 +550,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
         auto flush = [&]() {
           const int cnt = (int)(lp - mylist) >> 6;
           if (act) {
-            // WPE 4: two hits per iteration (independent chains), the odd one after
+            // WPE 4: FLUSH_H hits per iteration (independent chains), the rest one at a time
             auto run = [&](auto &acc) {
               using A = typename std::remove_reference<decltype(acc)>::type;
               using RA = decltype(A::fx);
               int q = 0;
-              if constexpr (WPE <= 4)
-                for (; q + 2 <= cnt; q += 2) {
-                  const int e0 = mylist[64 * q], e1 = mylist[64 * q + 64];
-                  lj_hit2<RA>(acc, xi - l64[3 * e0], yi - l64[3 * e0 + 1], zi - l64[3 * e0 + 2], xi - l64[3 * e1],
-                              yi - l64[3 * e1 + 1], zi - l64[3 * e1 + 2], k);
+              if constexpr (WPE <= 4) {
+                constexpr int H = FLUSH_H;
+                for (; q + H <= cnt; q += H) {
+                  double dx[H], dy[H], dz[H];
+#pragma unroll
+                  for (int h = 0; h < H; ++h) {
+                    const int e = mylist[64 * (q + h)];
+                    dx[h] = xi - l64[3 * e], dy[h] = yi - l64[3 * e + 1], dz[h] = zi - l64[3 * e + 2];
+                  }
+                  lj_hitn<RA, H>(acc, dx, dy, dz, k);
                 }
+              }
               for (; q < cnt; ++q) {
                 const int e = mylist[64 * q];
                 lj_hit<RA>(acc, xi - l64[3 * e], yi - l64[3 * e + 1], zi - l64[3 * e + 2], k);
