@@ -10,10 +10,11 @@
 //     multi-site molecules;
 //   * the lanes of a wavefront are n molecules x NS = min(8, floor(64 / n)) partner slices, and
 //     lane (i, s) scans staged partners s, s + NS, ...;
-//   * pass 1 runs the COM cutoff test in FP64 with the exact expression
-//     fma(dz, dz, fma(dy, dy, dx * dx)) < r_c^2 on d = r_i - (r_j + shift), so the set of
-//     interacting pairs is the brute-force set bit for bit, and lists the hits; pass 2 evaluates
-//     the listed pairs only;
+//   * pass 1 lists the candidates inside the COM cutoff and pass 2 evaluates the listed pairs
+//     only; the decision is always the exact FP64 test fma(dz, dz, fma(dy, dy, dx * dx)) < r_c^2
+//     on d = r_i - (r_j + shift), so the set of interacting pairs is the brute-force set bit for
+//     bit (the single-site FP32 path lists with an FP32 test whose threshold carries a proven
+//     rounding guard band and re-tests the listed pairs exactly in FP64);
 //   * the FP32 path (R = float) seeds reciprocals in FP32 and evaluates the single-site LJ force
 //     scalar and the multipole forces and torques in FP32; separations of LJ sites, the
 //     multi-site LJ terms (which share the energy's FP64 powers), pair energies (multipole
