@@ -137,27 +137,44 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_local(int32_t *in, int64_
   if (threadIdx.x == SCAN_THREADS - 1) bsum[blockIdx.x] = woff + incl;
 }
 
-// Exclusive scan of the nb tile totals in place (one block, sequential over chunks), total to
-// out[n] (and to out2[n2] when given).
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_top(int32_t *bsum, int64_t nb, int32_t *out, int64_t n,
-                                                           int32_t *out2, int64_t n2) {
-  __shared__ int wsum[SCAN_THREADS / 64];
+// Exclusive scan of the nb tile totals in place (one block of TOP_THREADS, TOP_ITEMS consecutive
+// totals per thread, sequential over chunks of TOP_TILE: one chunk up to 4096 tiles, i.e. 4 M
+// bins), total to out[n] (and to out2[n2] when given).
+constexpr int TOP_THREADS = 1024;
+constexpr int TOP_ITEMS = 4;
+constexpr int TOP_TILE = TOP_THREADS * TOP_ITEMS;
+__global__ __launch_bounds__(TOP_THREADS) void k_scan_top(int32_t *bsum, int64_t nb, int32_t *out, int64_t n,
+                                                          int32_t *out2, int64_t n2) {
+  __shared__ int wsum[TOP_THREADS / 64];
   __shared__ int carry_s;
   if (threadIdx.x == 0) carry_s = 0;
   __syncthreads();
-  for (int64_t c0 = 0; c0 < nb; c0 += SCAN_THREADS) {
-    const int64_t i = c0 + threadIdx.x;
-    const int v = i < nb ? bsum[i] : 0;
-    const int incl = wave_incl_scan(v);
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int64_t c0 = 0; c0 < nb; c0 += TOP_TILE) {
+    const int64_t base = c0 + (int64_t)threadIdx.x * TOP_ITEMS;
+    int v[TOP_ITEMS];
+    int tsum = 0;
+#pragma unroll
+    for (int k = 0; k < TOP_ITEMS; ++k) {
+      v[k] = base + k < nb ? bsum[base + k] : 0;
+      tsum += v[k];
+    }
+    const int incl = wave_incl_scan(tsum);
     if (lane == 63) wsum[w] = incl;
     __syncthreads();
-    int woff = 0;
-    for (int k = 0; k < w; ++k) woff += wsum[k];
+    // offsets of the waves: an inclusive scan of the 16 wave totals in the first lanes
+    const int wt = lane < TOP_THREADS / 64 ? wsum[lane] : 0;
+    const int wincl = wave_incl_scan(wt);
+    const int woff = __shfl(wincl, w, 64) - __shfl(wt, w, 64);
     const int carry = carry_s;
-    if (i < nb) bsum[i] = carry + woff + incl - v;
+    int run = carry + woff + incl - tsum;
+#pragma unroll
+    for (int k = 0; k < TOP_ITEMS; ++k) {
+      if (base + k < nb) bsum[base + k] = run;
+      run += v[k];
+    }
     __syncthreads();
-    if (threadIdx.x == SCAN_THREADS - 1) carry_s = carry + woff + incl;
+    if (threadIdx.x == TOP_THREADS - 1) carry_s = carry + woff + incl;
     __syncthreads();
   }
   if (threadIdx.x == 0) {
@@ -333,7 +350,7 @@ int launch_build(md_model *m, md_cells *c, const double *pos, const double *quat
   if ((rc = check_hip(hipGetLastError(), "k_bin"))) return rc;
   const int64_t nb = (nbin + SCAN_TILE - 1) / SCAN_TILE;
   k_scan_local<<<(unsigned)nb, SCAN_THREADS, 0, s>>>(c->count, nbin, c->lstart, c->bsum);
-  k_scan_top<<<1, SCAN_THREADS, 0, s>>>(c->bsum, nb, c->start, nbin, c->sub ? c->cstart : nullptr, c->ncell);
+  k_scan_top<<<1, TOP_THREADS, 0, s>>>(c->bsum, nb, c->start, nbin, c->sub ? c->cstart : nullptr, c->ncell);
   if ((rc = check_hip(hipGetLastError(), "k_scan"))) return rc;
   c->counts_zero = true;
   k_scatter<<<nblk(std::max<int64_t>(N, nbin), 256), 256, 0, s>>>(c->cellv, c->slot, order, c->lstart, c->bsum, N,

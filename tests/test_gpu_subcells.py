@@ -94,6 +94,31 @@ def test_subcell_rebuild_in_previous_order(md, oracle):
     _check_cells(cells.view(), oracle, moved, cfg["box"], cfg["model"]["rc"])
 
 
+@pytest.mark.parametrize("subcells,ncell_axis", [(True, 85), (False, 162)])
+def test_cell_starts_over_many_scan_chunks(md, oracle, subcells, ncell_axis):
+    """A sparse grid with more than 4 M bins (half-edge cells: 85^3 cells x 8; plain: 162^3 cells):
+    the scan of the tile totals runs over several chunks, and every start must still be the
+    oracle's (cell ids, starts and the stable order bit for bit)."""
+    rng = W.rng_for(91 + int(subcells))
+    N = 150_000
+    box = [ncell_axis * 2.5 + 0.01] * 3
+    pos = rng.uniform(0.0, box[0], size=(N, 3))
+    m = md.Model(W.lj_model(2.5), subcells=subcells)
+    cells = md.Cells()
+    md.build_cells(m, cells, dev(pos), None, None, box)
+    v = cells.view()
+    assert v["ncell"] == ncell_axis ** 3 and (8 if subcells else 1) * v["ncell"] > 4096 * 1024
+    if subcells:
+        _check_cells(v, oracle, pos, box, 2.5)
+    else:
+        ref_cell, _, ncell = oracle.bin_cells(pos, box, 2.5)
+        np.testing.assert_array_equal(v["cell_of"].cpu().numpy(), ref_cell)
+        start = v["cell_start"].cpu().numpy()
+        np.testing.assert_array_equal(np.diff(start), np.bincount(ref_cell, minlength=ncell))
+        assert start[0] == 0 and start[-1] == N
+        np.testing.assert_array_equal(v["perm"].cpu().numpy(), np.lexsort((np.arange(N), ref_cell)))
+
+
 def test_one_cells_object_switches_models(md, oracle):
     """One cells object built alternately for a model with and one without half-edge cells: each
     build carries its own order."""
