@@ -178,18 +178,21 @@ def measure_extra(md, W, torch, name, evals, steps, adjoint=False, half_shell=Fa
         ts = time.perf_counter() - t
         e.update({"steps_per_s": steps / ts, "step_interactions_per_s": P * steps / ts})
         if adjoint:
+            # with the parameter gradients (dpos, dquat, dparams), then dpos and dquat only
             md.build_cells(model, cells, dev(cfg["pos"]), dev(cfg["quat"]), None, cfg["box"])
-            md.forces_adjoint(model, cells, prec, 1.0, want_quat=multi)
-            torch.cuda.synchronize()
-            model.profile(True)
-            t = time.perf_counter()
-            for _ in range(evals):
-                md.forces_adjoint(model, cells, prec, 1.0, want_quat=multi)
-            torch.cuda.synchronize()
-            wall = (time.perf_counter() - t) / evals
-            ms, k = model.profile_read("adjoint")
-            model.profile(False)
-            e.update({"adjoint_ms": 1e3 * wall, "adjoint_interactions_per_s": P / wall})
+            for params, key in ((True, ""), (False, "_pos_quat_only")):
+                md.forces_adjoint(model, cells, prec, 1.0, want_quat=multi, want_params=params)
+                torch.cuda.synchronize()
+                model.profile(True)
+                t = time.perf_counter()
+                for _ in range(evals):
+                    md.forces_adjoint(model, cells, prec, 1.0, want_quat=multi, want_params=params)
+                torch.cuda.synchronize()
+                wall = (time.perf_counter() - t) / evals
+                ms, k = model.profile_read("adjoint")
+                model.profile(False)
+                e.update({"adjoint_ms" + key: 1e3 * wall, "adjoint_kernel_ms" + key: ms / k,
+                          "adjoint_interactions_per_s" + key: P / wall})
         out[prec] = e
     out["fp32_speedup_forces"] = out["fp64"]["forces_ms"] / out["fp32"]["forces_ms"]
     return out

@@ -276,7 +276,9 @@ int md_long_range_correction(const md_component_desc *comps, int32_t ncomp, cons
 /* Outputs:
  *   dpos    [N][3]  gU dU/dr_i (= -gU F_i)
  *   dquat   [N][4]  gU dU/dq_i with respect to the raw quaternion components (NULL allowed)
- *   dparams [md_param_count(m)] gU dU/d(parameters), layout as md_param_count (NULL allowed)
+ *   dparams [md_param_count(m)] gU dU/d(parameters), layout as md_param_count (NULL allowed:
+ *           the kernels then leave the parameter partials out of the pair loop, which makes a
+ *           dpos / dquat-only call markedly cheaper)
  * The molecule-pair set is the one fixed by the cutoff (U is differentiated piecewise).
  * Errors: MD_EINVAL, MD_EHIP. */
 int md_forces_adjoint(md_model *m, const md_cells *cells, int precision, double gU, double *dpos, double *dquat,

@@ -19,7 +19,9 @@
 namespace mdcell {
 namespace {
 
-template <int SL, int SC, int SD, int SQ> struct AdjAcc {
+// PRM: the parameter partials (peps, psig, pmom) are accumulated; without dU/d(parameters) they
+// are left out of the pair loop.
+template <int SL, int SC, int SD, int SQ, bool PRM = true> struct AdjAcc {
   static constexpr int NSITE = SL + SC + SD + SQ;
   static constexpr int NAX = SD + SQ > 0 ? SD + SQ : 1;
   static constexpr int NMOM = SC + SD + SQ > 0 ? SC + SD + SQ : 1;
@@ -30,9 +32,9 @@ template <int SL, int SC, int SD, int SQ> struct AdjAcc {
   int n;
 };
 
-template <int KA, int KB, int SL, int SC, int SD, int SQ, bool MIX, typename R>
+template <int KA, int KB, int SL, int SC, int SD, int SQ, bool MIX, typename R, bool PRM>
 __device__ __forceinline__ void adj_elec_group(const CompDev &A, const CompDev &B, const R (*vi)[3], const R *vj,
-                                               R dx, R dy, R dz, R krc3, AdjAcc<SL, SC, SD, SQ> &acc) {
+                                               R dx, R dy, R dz, R krc3, AdjAcc<SL, SC, SD, SQ, PRM> &acc) {
 #pragma clang fp contract(fast)  // products and sums fused where the compiler can (pair algebra only)
   using S = Slots<SL, SC, SD, SQ>;
   constexpr int NA = KA == KIND_CHG ? SC : (KA == KIND_DIP ? SD : SQ);
@@ -79,14 +81,14 @@ __device__ __forceinline__ void adj_elec_group(const CompDev &A, const CompDev &
           acc.ga[XA + a][k] += (double)(pm * ge);
         }
       }
-      acc.pmom[MA + a] += (double)(mb * t.t);
+      if constexpr (PRM) acc.pmom[MA + a] += (double)(mb * t.t);
     }
   }
 }
 
-template <int SL, int SC, int SD, int SQ, bool MIX, typename R>
+template <int SL, int SC, int SD, int SQ, bool MIX, typename R, bool PRM>
 __device__ __forceinline__ void adj_pair(const ModelDev *__restrict__ md, int ci, int cj, const R (*vi)[3],
-                                         const R *vj, R dx, R dy, R dz, AdjAcc<SL, SC, SD, SQ> &acc) {
+                                         const R *vj, R dx, R dy, R dz, AdjAcc<SL, SC, SD, SQ, PRM> &acc) {
 #pragma clang fp contract(fast)
   const CompDev &A = md->comp[ci];
   const CompDev &B = md->comp[cj];
@@ -108,9 +110,11 @@ __device__ __forceinline__ void adj_pair(const ModelDev *__restrict__ md, int ci
       // dU/dR = -24 eps (2 s^12 - s^6) / r^2 R
       const R gsc = -((R)p.eps24 * ir2) * (s6 * fma((R)2, s6, (R)-1));
       acc.gs[a][0] += (double)(gsc * rx), acc.gs[a][1] += (double)(gsc * ry), acc.gs[a][2] += (double)(gsc * rz);
-      const double u = (double)((R)p.eps4 * (s12 - s6)) - p.shift;
-      acc.peps[a] += u * p.pe;
-      acc.psig[a] += p.ps * ((double)((R)12 * s12 - (R)6 * s6) - p.csh);
+      if constexpr (PRM) {
+        const double u = (double)((R)p.eps4 * (s12 - s6)) - p.shift;
+        acc.peps[a] += u * p.pe;
+        acc.psig[a] += p.ps * ((double)((R)12 * s12 - (R)6 * s6) - p.csh);
+      }
     }
   }
   if constexpr (SC + SD + SQ > 0) {
@@ -157,9 +161,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int SL, int SC, int SD, int SQ>
-__device__ __forceinline__ void acc_zero(AdjAcc<SL, SC, SD, SQ> &acc) {
-  using Acc = AdjAcc<SL, SC, SD, SQ>;
+template <int SL, int SC, int SD, int SQ, bool PRM>
+__device__ __forceinline__ void acc_zero(AdjAcc<SL, SC, SD, SQ, PRM> &acc) {
+  using Acc = AdjAcc<SL, SC, SD, SQ, PRM>;
 #pragma unroll
   for (int a = 0; a < Acc::NSITE; ++a) acc.gs[a][0] = acc.gs[a][1] = acc.gs[a][2] = 0.0;
 #pragma unroll
@@ -172,9 +176,9 @@ __device__ __forceinline__ void acc_zero(AdjAcc<SL, SC, SD, SQ> &acc) {
 }
 
 // Add the slices of molecule lane l (lanes l + s hc, s = 1 .. NS - 1) to lane l, in slice order.
-template <int SL, int SC, int SD, int SQ>
-__device__ __forceinline__ void acc_gather(AdjAcc<SL, SC, SD, SQ> &acc, int hc, int NS) {
-  using Acc = AdjAcc<SL, SC, SD, SQ>;
+template <int SL, int SC, int SD, int SQ, bool PRM>
+__device__ __forceinline__ void acc_gather(AdjAcc<SL, SC, SD, SQ, PRM> &acc, int hc, int NS) {
+  using Acc = AdjAcc<SL, SC, SD, SQ, PRM>;
   const int lane = threadIdx.x & 63;
   const bool dst = lane < hc;
   auto add = [&](double &v, int src) {
@@ -192,9 +196,9 @@ __device__ __forceinline__ void acc_gather(AdjAcc<SL, SC, SD, SQ> &acc, int hc, 
 #pragma unroll
       for (int k = 0; k < 3; ++k) add(acc.ga[a][k], src);
 #pragma unroll
-    for (int a = 0; a < SL; ++a) add(acc.peps[a], src), add(acc.psig[a], src);
+    for (int a = 0; a < SL && PRM; ++a) add(acc.peps[a], src), add(acc.psig[a], src);
 #pragma unroll
-    for (int a = 0; a < Acc::NMOM; ++a) add(acc.pmom[a], src);
+    for (int a = 0; a < Acc::NMOM && PRM; ++a) add(acc.pmom[a], src);
     const int n = __shfl(acc.n, src);
     if (dst) acc.n += n;
   }
@@ -211,15 +215,17 @@ template <int SL, int SC, int SD, int SQ> struct PSlots {
 // in the force kernel; pass 1 lists the COM-cutoff hits, pass 2 recomputes each listed pair's
 // site terms into the lane's adjoint accumulators (the hits of a molecule split evenly over its
 // slice lanes), slices are then added in a fixed order.
-template <typename R, int SL, int SC, int SD, int SQ, bool MIX, bool SINGLE, int CAP, int W>
+// PRM: parameter gradients wanted (o.pgrad given); without them the pair loop leaves out the
+// parameter partials.
+template <typename R, int SL, int SC, int SD, int SQ, bool MIX, bool SINGLE, int CAP, int W, bool PRM>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 : 3))) void k_adjoint(
     CellsDev c, const ModelDev *__restrict__ md, const double *quat, double rc2, AdjOut o) {
   using S = Slots<SL, SC, SD, SQ>;
-  using Acc = AdjAcc<SL, SC, SD, SQ>;
+  using Acc = AdjAcc<SL, SC, SD, SQ, PRM>;
   using PS = PSlots<SL, SC, SD, SQ>;
   constexpr int NV = SINGLE ? 1 : S::nv;
   constexpr int LCAP = 32;
-  constexpr int NB = MIX ? 256 : PS::np;
+  constexpr int NB = !PRM ? 1 : (MIX ? 256 : PS::np);
   static_assert(CAP <= 256, "list entries are bytes");
   __shared__ double jp[CAP * 3 + 48];  // slack: the walk reads up to 2 NS - 1 slots past the window
   __shared__ R jv[CAP][NV * 3];
@@ -378,7 +384,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
           for (int k = 0; k < 4; ++k) o.dquat[4 * orig + k] = o.gU * dq[k];
         }
       }
-      if (o.pgrad) {
+      if (PRM && o.pgrad) {
         // this molecule's parameter partials (zero on non-leading lanes), then per component a
         // fixed-order wave sum added to the block row under the ABI column of each slot
         double pv[PS::np];
@@ -434,7 +440,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
       }
     }
   }
-  if (o.pgrad) {
+  if (PRM && o.pgrad) {
     __syncthreads();
     double *row = o.pgrad + (int64_t)blockIdx.x * ncol;
     for (int k = tid; k < ncol; k += 64 * W) {
@@ -450,10 +456,15 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
 template <typename R, int SL, int SC, int SD, int SQ, bool MIX, bool SINGLE, int CAP, int CAP1 = CAP>
 int launch_adj(const CellsDev &cd, const md_model *m, const double *quat, const AdjOut &o, int64_t nb, double mean,
                hipStream_t s) {
-  if (mean >= 16.0)
-    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP, 4><<<(unsigned)nb, 256, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
+  const bool prm = o.pgrad != nullptr;
+  if (mean >= 16.0 && prm)
+    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP, 4, true><<<(unsigned)nb, 256, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
+  else if (mean >= 16.0)
+    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP, 4, false><<<(unsigned)nb, 256, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
+  else if (prm)
+    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP1, 1, true><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
   else
-    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP1, 1><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
+    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP1, 1, false><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
   return check_hip(hipGetLastError(), "k_adjoint");
 }
 

@@ -91,6 +91,34 @@ def test_adjoint_matches_autograd_reference(md, refs, name, prec):
     assert e_par < bpar, msg
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["c1_sub", "c4_small", "c5_small", "mixture_small", "c5_dilute", "mixture4_small"])
+def test_adjoint_without_parameters(md, refs, name, prec):
+    """dpos and dquat only (no dparams): the kernels without the parameter partials must meet the
+    same bars against the autograd reference and agree with the full call to rounding (the
+    position and axis gradients are the same arithmetic)."""
+    c, ref = refs[name]
+    m = md.Model(c["model"])
+    cells = md.Cells()
+    ncomp = len(c["model"]["components"])
+    md.build_cells(m, cells, dev(c["pos"]), dev(c["quat"]), dev(c["comp"], torch.int32) if ncomp > 1 else None, c["box"])
+    gU = 0.75
+    multi = c["quat"] is not None
+    full = md.forces_adjoint(m, cells, prec, gU, want_quat=multi)
+    part = md.forces_adjoint(m, cells, prec, gU, want_quat=multi, want_params=False)
+    torch.cuda.synchronize()
+    assert part["dparams"] is None
+    bp, bq, _ = BARS[prec]
+    tight = 1e-13 if prec == "fp64" else 1e-6
+    dpos = part["dpos"].cpu().numpy()
+    assert rel_rms(dpos, gU * ref["dpos"]) < bp and elem_err(dpos, gU * ref["dpos"]) < 10 * bp
+    assert elem_err(dpos, full["dpos"].cpu().numpy()) < tight
+    if multi:
+        dq = part["dquat"].cpu().numpy()
+        assert rel_rms(dq, gU * ref["dquat"]) < bq and elem_err(dq, gU * ref["dquat"]) < 10 * bq
+        assert elem_err(dq, full["dquat"].cpu().numpy()) < tight
+
+
 def test_energy_autograd_function(md, refs):
     """EnergyFn: forward = md_forces energy, backward = md_forces_adjoint (gradients w.r.t. the
     position and quaternion tensors), chained through further torch operations."""
