@@ -268,6 +268,8 @@ int md_long_range_correction(const md_component_desc *comps, int32_t ncomp, cons
                              double *w_lrc);
 
 /* Gradient of gU * U for the built configuration, recomputing every pair (no stored pair list).
+ * Single-site models take one force evaluation: dU/dr_i = -F_i, U is linear in eps, sigma dU/dsigma
+ * is the virial W minus the shift's share, and the offset gradient sum_i dU/dr_i vanishes.
  * "The built configuration" is the library-owned copy that the last md_build_cells on `cells`
  * took of pos and quat (sorted COMs, quaternions and site vectors): the caller may change or free
  * its own pos / quat arrays after md_build_cells returns.  After md_step, that copy is the

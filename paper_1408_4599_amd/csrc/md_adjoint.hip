@@ -468,7 +468,30 @@ int launch_adj(const CellsDev &cd, const md_model *m, const double *quat, const 
   return check_hip(hipGetLastError(), "k_adjoint");
 }
 
+// Single-site LJ adjoint from one force evaluation (md_forces_adjoint): dpos = -gU F in place,
+// and, when dparams is given, the parameter gradients with the same per-pair-end factors as the
+// adjoint kernel (pe, ps, csh of the site pair) summed over both ends of every pair:
+// gU (2 pe U, 2 ps (W / (4 eps) - P csh)), and the offset gradient sum_i dU/dr_i, which is zero
+// (U does not change under a common translation; the single site sits at the centre).
+__global__ __launch_bounds__(256) void k_lj_adjoint_finish(double *dpos, int64_t n3, double gU, const double *uw,
+                                                           const int64_t *npairs, LJPair p, double *dparams) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n3) dpos[i] = -gU * dpos[i];
+  if (dparams && i == 0) {
+    dparams[0] = gU * (2.0 * p.pe * uw[0]);
+    dparams[1] = gU * (2.0 * p.ps * (uw[1] / p.eps4 - (double)npairs[0] * p.csh));
+    dparams[2] = dparams[3] = dparams[4] = 0.0;
+  }
+}
+
 }  // namespace
+
+int launch_lj_adjoint_finish(const md_model *m, double *dpos, int64_t N, double gU, const double *uw,
+                             const int64_t *npairs, double *dparams, hipStream_t s) {
+  k_lj_adjoint_finish<<<(unsigned)((3 * N + 255) / 256), 256, 0, s>>>(dpos, 3 * N, gU, uw, npairs,
+                                                                     m->host.lj[0][0][0][0], dparams);
+  return check_hip(hipGetLastError(), "k_lj_adjoint_finish");
+}
 
 CellsDev cells_dev(const md_cells *c);
 
@@ -480,9 +503,8 @@ int launch_adjoint(md_model *m, const md_cells *c, int precision, const AdjOut &
   const bool f32 = precision == MD_FP32;
   const Shape &S = m->shape;
   const double mean = (double)c->N / (double)c->ncell;
-  if (m->single_site)
-    return f32 ? launch_adj<float, 1, 0, 0, 0, false, true, 256, 128>(cd, m, nullptr, o, nb, mean, s)
-               : launch_adj<double, 1, 0, 0, 0, false, true, 256, 128>(cd, m, nullptr, o, nb, mean, s);
+  if (m->single_site)  // md_forces_adjoint takes these models through the force kernel
+    return set_error(MD_EINVAL, "launch_adjoint: single-site model");
   if (m->fixed_shape && S.lj == 2 && S.chg == 0 && S.dip == 0 && S.quad == 1)
     return f32 ? launch_adj<float, 2, 0, 0, 1, false, false, 256, 64>(cd, m, quat, o, nb, mean, s)
                : launch_adj<double, 2, 0, 0, 1, false, false, 256, 64>(cd, m, quat, o, nb, mean, s);

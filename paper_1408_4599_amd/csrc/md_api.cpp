@@ -724,8 +724,23 @@ int md_forces_adjoint(md_model *m, const md_cells *c, int precision, double gU, 
   if (!c->built || c->model != m) return set_error(MD_EINVAL, "md_forces_adjoint: cells not built with this model");
   hipStream_t s = (hipStream_t)stream;
   m->last_stream = s;
-  const int64_t nb = pair_blocks(c->ncell);
   int rc;
+  if (m->single_site) {
+    // One LJ site at the centre: gU dU/dr_i = -gU F_i, and the parameter gradients follow from one
+    // force evaluation (U is linear in eps; sigma dU/dsigma is the virial minus the shift's share;
+    // the offset gradient sum_i dU/dr_i vanishes), so the force kernel serves as the adjoint.
+    double *uw5 = m->uw + 24;
+    int64_t *np = (int64_t *)(m->uw + 32);
+    hipEvent_t ev;
+    prof_begin(m, PROF_ADJ, s, &ev);
+    rc = forces_impl(m, c, precision, dpos, nullptr, nullptr, nullptr, nullptr, uw5, np, nullptr, s, dparams != nullptr);
+    if (!rc) rc = launch_lj_adjoint_finish(m, dpos, c->N, gU, uw5, np, dparams, s);
+    if (!rc && dquat) rc = launch_fill_f64(dquat, 4 * c->N, 0.0, s);
+    prof_end(m, PROF_ADJ, s, ev);
+    if (rc) return rc;
+    return sync_check(m, s);
+  }
+  const int64_t nb = pair_blocks(c->ncell);
   double *pg = nullptr;
   if (dparams && m->nparam > 0) {
     if ((rc = grow(m->pgrad, m->cap_pgrad, nb * m->nparam, "param partials"))) return rc;

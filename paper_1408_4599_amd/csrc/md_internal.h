@@ -206,6 +206,10 @@ int launch_leapfrog(md_model *m, double *pos, double *vel, double *quat, double 
                     double *kin_rows, int64_t *kin_nrows, hipStream_t s);
 int launch_adjoint(md_model *m, const md_cells *c, int precision, const AdjOut &o, const double *quat,
                    hipStream_t s, int64_t *nblocks);
+// single-site LJ adjoint after the force kernel: dpos = -gU F in place; dparams[0..4] (NULL
+// allowed) from U, W (uw[0], uw[1]) and the pair count
+int launch_lj_adjoint_finish(const md_model *m, double *dpos, int64_t N, double gU, const double *uw,
+                             const int64_t *npairs, double *dparams, hipStream_t s);
 // device address of the static scratch array of md_forces_noalloc on the current device (looked
 // up once per device with hipGetSymbolAddress; md_pair.hip)
 int noalloc_scratch(void **ptr);
