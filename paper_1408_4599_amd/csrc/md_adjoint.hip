@@ -217,13 +217,13 @@ template <int SL, int SC, int SD, int SQ> struct PSlots {
 // slice lanes), slices are then added in a fixed order.
 // PRM: parameter gradients wanted (o.pgrad given); without them the pair loop leaves out the
 // parameter partials.
-template <typename R, int SL, int SC, int SD, int SQ, bool MIX, bool SINGLE, int CAP, int W, bool PRM>
+template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP, int W, bool PRM>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 : 3))) void k_adjoint(
     CellsDev c, const ModelDev *__restrict__ md, const double *quat, double rc2, AdjOut o) {
   using S = Slots<SL, SC, SD, SQ>;
   using Acc = AdjAcc<SL, SC, SD, SQ, PRM>;
   using PS = PSlots<SL, SC, SD, SQ>;
-  constexpr int NV = SINGLE ? 1 : S::nv;
+  constexpr int NV = S::nv;
   constexpr int LCAP = 32;
   constexpr int NB = !PRM ? 1 : (MIX ? 256 : PS::np);
   static_assert(CAP <= 256, "list entries are bytes");
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
         const int sidx = hs + (hc > 0 ? iloc : 0);
         if (act) xi = c.sx[sidx], yi = c.sy[sidx], zi = c.sz[sidx];
         if (MIX) ci = c.scomp[sidx];
-        if (!SINGLE) {
+        {
           const double *v = c.svec + (int64_t)sidx * NV * 3;
 #pragma unroll
           for (int k = 0; k < NV; ++k) vi[k][0] = (R)v[3 * k], vi[k][1] = (R)v[3 * k + 1], vi[k][2] = (R)v[3 * k + 2];
@@ -314,12 +314,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
           jp[3 * t + 1] = c.sy[src] + nb.sh[k][1];
           jp[3 * t + 2] = c.sz[src] + nb.sh[k][2];
           if (MIX) jc_[t] = c.scomp[src];
-          if (!SINGLE) {
+          {
             const double *v = c.svec + (int64_t)src * NV * 3;
 #pragma unroll
             for (int q = 0; q < NV * 3; ++q) jv[t][q] = (R)v[q];
-          } else {
-            jv[t][0] = jv[t][1] = jv[t][2] = (R)0;
           }
         }
         __syncthreads();
@@ -453,18 +451,18 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(MIX ? 1 
 
 // Dense cells (mean occupancy >= 16) are shared by four wavefronts with windows of CAP molecules,
 // sparser ones take one wavefront each with windows of CAP1 (smaller LDS per one-wave block).
-template <typename R, int SL, int SC, int SD, int SQ, bool MIX, bool SINGLE, int CAP, int CAP1 = CAP>
+template <typename R, int SL, int SC, int SD, int SQ, bool MIX, int CAP, int CAP1 = CAP>
 int launch_adj(const CellsDev &cd, const md_model *m, const double *quat, const AdjOut &o, int64_t nb, double mean,
                hipStream_t s) {
   const bool prm = o.pgrad != nullptr;
   if (mean >= 16.0 && prm)
-    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP, 4, true><<<(unsigned)nb, 256, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
+    k_adjoint<R, SL, SC, SD, SQ, MIX, CAP, 4, true><<<(unsigned)nb, 256, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
   else if (mean >= 16.0)
-    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP, 4, false><<<(unsigned)nb, 256, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
+    k_adjoint<R, SL, SC, SD, SQ, MIX, CAP, 4, false><<<(unsigned)nb, 256, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
   else if (prm)
-    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP1, 1, true><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
+    k_adjoint<R, SL, SC, SD, SQ, MIX, CAP1, 1, true><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
   else
-    k_adjoint<R, SL, SC, SD, SQ, MIX, SINGLE, CAP1, 1, false><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
+    k_adjoint<R, SL, SC, SD, SQ, MIX, CAP1, 1, false><<<(unsigned)nb, 64, 0, s>>>(cd, m->dev, quat, m->host.rc2, o);
   return check_hip(hipGetLastError(), "k_adjoint");
 }
 
@@ -506,14 +504,14 @@ int launch_adjoint(md_model *m, const md_cells *c, int precision, const AdjOut &
   if (m->single_site)  // md_forces_adjoint takes these models through the force kernel
     return set_error(MD_EINVAL, "launch_adjoint: single-site model");
   if (m->fixed_shape && S.lj == 2 && S.chg == 0 && S.dip == 0 && S.quad == 1)
-    return f32 ? launch_adj<float, 2, 0, 0, 1, false, false, 256, 64>(cd, m, quat, o, nb, mean, s)
-               : launch_adj<double, 2, 0, 0, 1, false, false, 256, 64>(cd, m, quat, o, nb, mean, s);
+    return f32 ? launch_adj<float, 2, 0, 0, 1, false, 256, 64>(cd, m, quat, o, nb, mean, s)
+               : launch_adj<double, 2, 0, 0, 1, false, 256, 64>(cd, m, quat, o, nb, mean, s);
   if (m->fixed_shape && S.lj == 3 && S.chg == 0 && S.dip == 1 && S.quad == 0)
-    return f32 ? launch_adj<float, 3, 0, 1, 0, false, false, 256, 64>(cd, m, quat, o, nb, mean, s)
-               : launch_adj<double, 3, 0, 1, 0, false, false, 256, 64>(cd, m, quat, o, nb, mean, s);
-  return f32 ? launch_adj<float, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, false, 64>(cd, m, quat, o, nb,
+    return f32 ? launch_adj<float, 3, 0, 1, 0, false, 256, 64>(cd, m, quat, o, nb, mean, s)
+               : launch_adj<double, 3, 0, 1, 0, false, 256, 64>(cd, m, quat, o, nb, mean, s);
+  return f32 ? launch_adj<float, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64>(cd, m, quat, o, nb,
                                                                                                     mean, s)
-             : launch_adj<double, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, false, 64>(cd, m, quat, o, nb,
+             : launch_adj<double, MD_MAX_LJ, MD_MAX_CHG, MD_MAX_DIP, MD_MAX_QUAD, true, 64>(cd, m, quat, o, nb,
                                                                                                      mean, s);
 }
 
