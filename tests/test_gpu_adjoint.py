@@ -119,6 +119,31 @@ def test_adjoint_without_parameters(md, refs, name, prec):
         assert elem_err(dq, full["dquat"].cpu().numpy()) < tight
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("half_shell", [False, True])
+def test_single_site_adjoint_through_the_force_kernels(md, refs, prec, half_shell):
+    """Single-site models take the adjoint from one force evaluation (dU/dr = -F; eps and sigma
+    gradients from U, W and the pair count): through the full-shell and the half-shell force
+    kernel alike, against the autograd reference, with and without parameter gradients, at two
+    values of gU."""
+    c, ref = refs["c1_sub"]
+    m = md.Model(c["model"], half_shell=half_shell)
+    cells = md.Cells()
+    md.build_cells(m, cells, dev(c["pos"]), None, None, c["box"])
+    bp, _, bpar = BARS[prec]
+    want = _abi_params(c["model"], ref["params"])
+    for gU in (0.75, -2.0):
+        g = md.forces_adjoint(m, cells, prec, gU, want_quat=False)
+        h = md.forces_adjoint(m, cells, prec, gU, want_quat=False, want_params=False)
+        torch.cuda.synchronize()
+        for d in (g["dpos"], h["dpos"]):
+            dpos = d.cpu().numpy()
+            assert rel_rms(dpos, gU * ref["dpos"]) < bp and elem_err(dpos, gU * ref["dpos"]) < 10 * bp
+        par = g["dparams"].cpu().numpy()
+        assert par.shape == want.shape
+        assert np.abs(par - gU * want).max() / np.abs(gU * want).max() < bpar
+
+
 def test_energy_autograd_function(md, refs):
     """EnergyFn: forward = md_forces energy, backward = md_forces_adjoint (gradients w.r.t. the
     position and quaternion tensors), chained through further torch operations."""
