@@ -238,6 +238,51 @@ def build_sweep(md, W, torch, nbuild=10, subcells=True):
                                     "with half-edge cells)"}), flush=True)
 
 
+def step_sweep(md, W, torch):
+    """md_step throughput of homogeneous LJTS fluids (rho = 0.75, T = 0.9, r_c = 2.5, the C2
+    configuration) from 16 384 to 8 388 608 molecules on one GPU: FP32 path, half-edge cells, an
+    energies row every step, as in the benchmark's timed steps.  The GPU is first kept busy for
+    about 0.3 s (its first steps in a process run a few per cent slower); each size then takes 10
+    untimed steps and 50 to 500 timed ones."""
+    model = md.Model(W.lj_model(2.5, shift=True), subcells=True)
+    pos, box = W.fcc_positions_device(64, 0.75, 24084599, "cuda")
+    vel = torch.zeros_like(pos)
+    cells = md.Cells()
+    md.step(model, cells, pos, vel, None, None, None, box, 0.002, 700, "fp32")
+    torch.cuda.synchronize()
+    cells.close()
+    del pos, vel
+    rows = []
+    for n in (16, 24, 32, 48, 64, 96, 128):
+        pos, box = W.fcc_positions_device(n, 0.75, 24084599 + n, "cuda")
+        N = pos.shape[0]
+        g = torch.Generator(device="cuda")
+        g.manual_seed(n)
+        vel = torch.randn((N, 3), generator=g, device="cuda", dtype=torch.float64) * math.sqrt(0.9)
+        vel -= vel.mean(dim=0)
+        cells = md.Cells()
+        md.build_cells(model, cells, pos, None, None, box)
+        P = int(md.forces(model, cells, "fp32", torque=False, per_molecule=False)["npairs"].item())
+        nsteps = max(50, min(500, int(1e8 / N)))
+        en = torch.empty((nsteps, 4), dtype=torch.float64, device="cuda")
+        md.step(model, cells, pos, vel, None, None, None, box, 0.002, 10, "fp32", en)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        md.step(model, cells, pos, vel, None, None, None, box, 0.002, nsteps, "fp32", en)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / nsteps
+        rows.append({"N": N, "cells": int(np.prod(cells.view()["nc"])), "interacting_pairs": P, "steps": nsteps,
+                     "ms_per_step": 1e3 * dt, "interactions_per_s": P / dt, "molecule_steps_per_s": N / dt})
+        print(f"[bench] step N={N}: {1e3 * dt:.4f} ms, {P / dt:.3e} interactions/s", file=sys.stderr, flush=True)
+        cells.close()
+        del pos, vel, en
+        torch.cuda.empty_cache()
+    print(json.dumps({"step_sweep": rows, "precision": "fp32", "half_edge_cells": True,
+                      "note": "LJTS rho = 0.75, T = 0.9, r_c = 2.5, dt = 0.002; md_step with cell rebuild, "
+                              "forces, leapfrog and an energies row every step; rates from the wall time"}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +294,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle rows timed (0: auto)")
     ap.add_argument("--quick", action="store_true", help="short run for profilers: few steps, no extras")
+    ap.add_argument("--step-sweep", action="store_true", help="md_step throughput from 2^14 to 2^23 molecules")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run 3 plain device copies of this many MiB (HBM byte-counter calibration)")
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
@@ -273,6 +319,9 @@ def main():
     torch.cuda.set_device(0)
     if args.build_sweep:
         build_sweep(md, W, torch, subcells=not args.no_subcells)
+        return
+    if args.step_sweep:
+        step_sweep(md, W, torch)
         return
     t0 = time.time()
     cfg = W.make(args.workload)
