@@ -231,10 +231,11 @@ int md_forces_noalloc(md_model *m, const md_cells *cells, int precision, double 
  * I_k = 0).  pos, vel [N][3], quat [N][4] (NULL for single-site models), angmom [N][3] (NULL
  * likewise) are updated in place.  energies [nsteps][4] (NULL allowed) receives per step
  * U(t), K_trans(t) (v(t) = mean of the half-step velocities), K_rot(t), W(t).  With energies
- * and no thermostat, each step's reduction runs on a stream owned by the model (default
- * priority), ordered after the step by an event and overlapping the next step; before the call
- * returns, the caller's stream waits for the last of them, so every result is ordered on the
- * caller's stream as usual.  Errors as md_build_cells and md_forces. */
+ * or a thermostat (and nsteps > 1), each step's reduction, and the thermostat's rescaling, run
+ * on a stream owned by the model (default priority), ordered after the step by an event and
+ * overlapping the next step's cell build and forces; the next leapfrog waits for them, and
+ * before the call returns the caller's stream waits for the last of them, so every result is
+ * ordered on the caller's stream as usual.  Errors as md_build_cells and md_forces. */
 int md_step(md_model *m, md_cells *cells, double *pos, double *vel, double *quat, double *angmom,
             const int32_t *comp, int64_t N, const double box[3], double dt, int64_t nsteps, int precision,
             double *energies, void *stream);

@@ -581,9 +581,11 @@ int md_step(md_model *m, md_cells *c, double *pos, double *vel, double *quat, do
     m->cap_step = N;
   }
   const bool nvt = m->T_target > 0.0;
-  // with an energies row and no thermostat, each step's reduction goes to the side stream and
-  // overlaps the next step; the pair and kinetic partial rows then alternate between two slots
-  const bool overlap = energies && !nvt && nsteps > 1;
+  // with an energies row or the thermostat, each step's reduction (and the thermostat's velocity
+  // rescaling) goes to the side stream and overlaps the next step's build and forces, which do
+  // not read the velocities; the next leapfrog waits for it.  The pair and kinetic partial rows
+  // then alternate between two slots
+  const bool overlap = (energies || nvt) && nsteps > 1;
   int64_t slot_sz = 0;
   // an error return after a side-stream reduction has been queued first orders the caller's
   // stream after the last one, so that no queued reduction writes `energies` after the return
@@ -621,8 +623,12 @@ int md_step(md_model *m, md_cells *c, double *pos, double *vel, double *quat, do
     prof_begin(m, PROF_STEP, s, &ev);
     double *kin = part + nbp * PARTIAL_COLS;  // after the pair partials
     int64_t nkin = 0;
-    rc = launch_leapfrog(m, pos, vel, quat, angmom, m->host.ncomp > 1 ? comp : nullptr, N, box, dt, m->force,
-                         m->torque, kin, &nkin, s);
+    // the previous step's velocity rescaling (side stream) precedes this leapfrog
+    rc = (overlap && nvt && st >= 1) ? check_hip(hipStreamWaitEvent(s, m->ev_red[(st - 1) & 1], 0), "hipStreamWaitEvent")
+                                     : MD_OK;
+    if (!rc)
+      rc = launch_leapfrog(m, pos, vel, quat, angmom, m->host.ncomp > 1 ? comp : nullptr, N, box, dt, m->force,
+                           m->torque, kin, &nkin, s);
     // energies row: U, W from the pair partials and K_trans, K_rot from the leapfrog's, in one
     // reduction (skipped when neither energies nor the thermostat need it); the thermostat then
     // rescales the new half-step velocities from the reduced K(t) and degrees of freedom
@@ -630,13 +636,15 @@ int md_step(md_model *m, md_cells *c, double *pos, double *vel, double *quat, do
       rc = check_hip(hipEventRecord(m->ev_leap[slot], s), "hipEventRecord");
       if (!rc) rc = check_hip(hipStreamWaitEvent(m->side, m->ev_leap[slot], 0), "hipStreamWaitEvent");
       if (!rc) rc = launch_reduce_forces(m, nbp, part, m->uw + 8, nullptr, erow, m->side, kin, nkin);
+      if (!rc && nvt)
+        rc = launch_rescale(m, vel, angmom, m->host.ncomp > 1 ? comp : nullptr, N, m->uw + 13, m->T_target, m->side);
       if (!rc) rc = check_hip(hipEventRecord(m->ev_red[slot], m->side), "hipEventRecord");
       if (!rc) last_red = slot;
     } else if (!rc && (erow || nvt)) {
       rc = launch_reduce_forces(m, nbp, part, m->uw + 8, nullptr, erow, s, kin, nkin);
+      if (!rc && nvt)
+        rc = launch_rescale(m, vel, angmom, m->host.ncomp > 1 ? comp : nullptr, N, m->uw + 13, m->T_target, s);
     }
-    if (!rc && nvt)
-      rc = launch_rescale(m, vel, angmom, m->host.ncomp > 1 ? comp : nullptr, N, m->uw + 13, m->T_target, s);
     prof_end(m, PROF_STEP, s, ev);
     if (rc) {
       // a reduction queued on the side stream whose event was not recorded: wait for all of it
